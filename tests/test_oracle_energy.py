@@ -1,0 +1,125 @@
+"""Pins for the subspace iteration, the energy assembly and the frequency rule
+(Eqs. 6 and 10, Algorithm 1, Sec. 3)."""
+import numpy as np
+import pytest
+
+from oracle import chi0, coulomb, energy, fd, quadrature, subspace
+from paper_2504_01816_amd import synth
+
+
+def test_frequency_rule_integrates_known_functions():
+    om, W = quadrature.frequency_grid(8, 1.0)
+    assert np.all(np.diff(om) < 0)                        # high -> low
+    assert abs(np.sum(W / (1 + om ** 2)) - np.pi / 2) < 2e-6
+    om32, W32 = quadrature.frequency_grid(64, 1.0)
+    assert abs(np.sum(W32 * np.exp(-om32)) - 1.0) < 1e-10
+    assert abs(np.sum(W32 / (1 + om32 ** 2)) - np.pi / 2) < 1e-12
+
+
+def test_trace_log_identity():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((12, 12))
+    C = -(A @ A.T) / 10.0                                  # negative semidefinite
+    mu = np.linalg.eigvalsh(C)
+    L = np.linalg.cholesky(np.eye(12) - C)
+    assert abs(np.sum(subspace.g(mu)) - (2 * np.sum(np.log(np.diag(L))) + np.trace(C))) < 1e-12
+    assert np.all(subspace.g(mu) <= 0)
+
+
+def test_cholesky_orthonormalisation_is_positive_diagonal_qr():
+    R = np.random.default_rng(1).standard_normal((50, 7))
+    V = subspace.chol_orthonormalize(R)
+    np.testing.assert_allclose(V.T @ V, np.eye(7), atol=1e-13)
+    Q, T = np.linalg.qr(R)
+    Q = Q * np.sign(np.diag(T))[None, :]
+    np.testing.assert_allclose(V, Q, atol=1e-12)
+
+
+def _uniform_lambda(shape, h, omega):
+    n0, n1, n2 = shape
+    kap = (fd.symbol_1d(2 * np.pi * np.arange(n2) / n2, h)[:, None, None]
+           + fd.symbol_1d(2 * np.pi * np.arange(n1) / n1, h)[None, :, None]
+           + fd.symbol_1d(2 * np.pi * np.arange(n0) / n0, h)[None, None, :]).reshape(-1)
+    vol = np.prod(shape) * h ** 3
+    lam = -(8 * np.pi / vol) / (kap ** 2 / 4 + omega ** 2)
+    lam[0] = 0.0
+    return lam, kap
+
+
+def test_uniform_potential_spectrum_closed_form():
+    shape, h, om = (6, 6, 6), 0.5, 0.8
+    c = synth.uniform_cell(shape, h, v0=0.3)
+    X = chi0.chi0_sum_over_states(c.vloc, shape, h, 1, om).real
+    N = coulomb.nu_sqrt_dense(shape, h)
+    lam = np.sort(np.linalg.eigvalsh(N @ X @ N))
+    ref, _ = _uniform_lambda(shape, h, om)
+    np.testing.assert_allclose(lam, np.sort(ref), atol=1e-13)
+
+
+def test_uniform_potential_subspace_iteration_first_shell():
+    # 12^3 grid, one occupied state; the 6-fold first shell has the largest |lambda|
+    shape, h, om = (12, 12, 12), 0.5, 1.0
+    c = synth.uniform_cell(shape, h, v0=0.0)
+    ref, kap = _uniform_lambda(shape, h, om)
+    shell = np.sort(ref)[:6]
+    V0 = np.random.default_rng(3).standard_normal((c.nd, 6))
+    res = energy.rpa_energy(c.vloc, c.psi.T, c.eps, shape, h, V0, [om], [1.0], 1e-12, 2000, 40)
+    np.testing.assert_allclose(np.sort(res["mu"][0]), shell, rtol=1e-9)
+    np.testing.assert_allclose(res["E_c"], np.sum(subspace.g(shell)) / (2 * np.pi), rtol=1e-9)
+    # per-mode exact frequency integral vs a fine rule on the rational map
+    a = 8 * np.pi / (c.nd * h ** 3)
+    k1 = np.sort(kap)[1]
+    exact = 0.5 * (np.sqrt(a + k1 ** 2 / 4) - k1 / 2) - a / (2 * k1)
+    omg, W = quadrature.frequency_grid(200, 1.0)
+    quad = np.sum(W * subspace.g(-a / (k1 ** 2 / 4 + omg ** 2))) / (2 * np.pi)
+    assert abs(quad - exact) <= 1e-11 * abs(exact)
+
+
+@pytest.fixture(scope="module")
+def cell6():
+    return synth.small_cell(n=6, h=0.5, n_wells=2, n_occ=3, seed=11)
+
+
+def _dense_chi0t(c, om):
+    X = chi0.chi0_sum_over_states(c.vloc, c.shape, c.h, c.n_occ, om).real
+    N = coulomb.nu_sqrt_dense(c.shape, c.h)
+    return N @ X @ N
+
+
+def test_full_rank_single_iteration_is_the_direct_method(cell6):
+    # V = I (N_r = N_d): C is the whole chi0~ and E is Eq. 6 over all eigenvalues
+    c, om = cell6, 0.6
+    R, _ = energy.chi0_tilde_apply(np.eye(c.nd), c.vloc, c.psi.T, c.eps, om, c.shape, c.h,
+                                   1e-13, 3000)
+    E, mu, C = subspace.ritz_energy(np.eye(c.nd), R, 1.0)
+    lam = np.linalg.eigvalsh(_dense_chi0t(c, om))
+    assert abs(E - np.sum(subspace.g(lam)) / (2 * np.pi)) <= 1e-10 * abs(E)
+
+
+def test_converged_ritz_values_are_the_most_negative_eigenvalues(cell6):
+    c, om = cell6, 0.6
+    lam = np.sort(np.linalg.eigvalsh(_dense_chi0t(c, om)))
+    # a block of 6 ends at a spectral gap (lambda_7 / lambda_6 ~ 0.43), so it converges fast
+    V0 = np.random.default_rng(4).standard_normal((c.nd, 6))
+    res = energy.rpa_energy(c.vloc, c.psi.T, c.eps, c.shape, c.h, V0, [om], [1.0], 1e-13, 3000,
+                            200, ec_tol=1e-15)
+    np.testing.assert_allclose(np.sort(res["mu"][0]), lam[:6], rtol=1e-9, atol=1e-12)
+    assert res["E_c"] < 0 and np.all(res["mu"][0] <= 1e-14)
+    # Ritz values are bounded by the extreme eigenvalues at every iteration
+    assert np.all(np.diff(res["history"][0][1:]) <= 1e-14)   # energy decreases monotonically
+
+
+def test_warm_and_independent_modes_agree_at_convergence(cell6):
+    c = cell6
+    # three frequencies at which a 6-block ends at a spectral gap (ratio ~0.45)
+    om, W = np.array([1.5, 0.9, 0.5]), np.array([0.4, 0.3, 0.3])
+    V0 = np.random.default_rng(5).standard_normal((c.nd, 6))
+    kw = dict(ec_tol=1e-13)
+    a = energy.rpa_energy(c.vloc, c.psi.T, c.eps, c.shape, c.h, V0, om, W, 1e-13, 3000, 100,
+                          mode="warm", **kw)
+    b = energy.rpa_energy(c.vloc, c.psi.T, c.eps, c.shape, c.h, V0, om, W, 1e-13, 3000, 100,
+                          mode="independent", **kw)
+    assert np.all(a["n_iter"] < 100) and np.all(b["n_iter"] < 100)
+    assert abs(a["E_c"] - b["E_c"]) <= 1e-9 * abs(a["E_c"])
+    # warm starts need fewer subspace iterations at the lower frequencies
+    assert a["n_iter"][1:].sum() <= b["n_iter"][1:].sum()
