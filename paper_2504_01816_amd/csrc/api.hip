@@ -1,0 +1,681 @@
+// C ABI of the gfx950 RPA library: argument validation (host only), workspace carving and
+// the drivers that sequence the kernels of the hot path.
+//
+// Call structure (Algorithm 1):
+//   rpa_energy            for each cell: V <- chol-orthonormalise(V0); for each frequency
+//                         (given order, highest first): rpa_subspace_iter
+//   rpa_subspace_iter     repeat: u = nu^{1/2} V; D = chi0 u; R = nu^{1/2} D; C = sym(V^T R);
+//                         E = W/(2pi)(ln det(I-C) + tr C); M = R^T R = L L^T; V = R L^{-T}
+//   rpa_apply_chi0        per chunk of trial vectors: projector coefficients, projected
+//                         right-hand sides, batched COCG, Delta rho
+//   rpa_energy_backward   per frequency: eig(C_m), W = V_m Y, u = nu^{1/2} W, COCG with the
+//                         complex solutions kept, gradient accumulation
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace rpa {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void fd_weights(double w[7]) {
+    // Centred second-derivative weights of order 12 (radius 6):
+    // w_p = 2 (-1)^{p+1} (6!)^2 / (p^2 (6-p)! (6+p)!),  w_0 = -2 sum_p w_p.
+    w[0] = -5369.0 / 1800.0;
+    w[1] = 12.0 / 7.0;
+    w[2] = -15.0 / 56.0;
+    w[3] = 10.0 / 189.0;
+    w[4] = -1.0 / 112.0;
+    w[5] = 2.0 / 1925.0;
+    w[6] = -1.0 / 16632.0;
+}
+
+namespace {
+
+constexpr int kVersion = 10000;
+
+struct Opts {
+    int precision = RPA_FP64;
+    int cocg_max_iter = 5000;
+    double cocg_tol = 1e-8;
+    int subspace_iters = 50;
+    int freq_mode = RPA_WARM;
+    double ec_tol = 1e-8;
+    double refine_tol = 1e-4;
+    int max_systems = 0;
+};
+
+int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+int read_opts(const rpa_options* o, Opts* out) {
+    Opts d;
+    if (o) {
+        d.precision = o->precision;
+        d.cocg_max_iter = o->cocg_max_iter;
+        d.cocg_tol = o->cocg_tol;
+        d.subspace_iters = o->subspace_iters;
+        d.freq_mode = o->freq_mode;
+        d.ec_tol = o->ec_tol;
+        d.refine_tol = o->refine_tol;
+        d.max_systems = o->max_systems;
+    }
+    if (d.precision != RPA_FP64 && d.precision != RPA_MIXED)
+        return fail(RPA_EINVAL, "options.precision must be RPA_FP64 or RPA_MIXED");
+    if (d.cocg_max_iter < 1) return fail(RPA_EINVAL, "options.cocg_max_iter must be >= 1");
+    if (!(d.cocg_tol > 0.0 && d.cocg_tol < 1.0))
+        return fail(RPA_EINVAL, "options.cocg_tol must be in (0, 1)");
+    if (d.subspace_iters < 1) return fail(RPA_EINVAL, "options.subspace_iters must be >= 1");
+    if (d.freq_mode != RPA_WARM && d.freq_mode != RPA_INDEPENDENT)
+        return fail(RPA_EINVAL, "options.freq_mode must be RPA_WARM or RPA_INDEPENDENT");
+    if (!std::isfinite(d.ec_tol)) return fail(RPA_EINVAL, "options.ec_tol must be finite");
+    if (!(d.refine_tol > 0.0 && d.refine_tol < 1.0))
+        return fail(RPA_EINVAL, "options.refine_tol must be in (0, 1)");
+    if (d.max_systems < 0) return fail(RPA_EINVAL, "options.max_systems must be >= 0");
+    if (d.precision == RPA_MIXED) return fail(RPA_ENOTIMPL, "RPA_MIXED is not available yet");
+    *out = d;
+    return RPA_OK;
+}
+
+// Geometry-only validation (used by the workspace query).
+int check_geometry(const rpa_cell* c) {
+    if (!c) return fail(RPA_EINVAL, "cell is NULL");
+    if (c->n[0] < 7 || c->n[1] < 7 || c->n[2] < 12)
+        return fail(RPA_EINVAL, "grid must have n[0], n[1] >= 7 and n[2] >= 12");
+    const int64_t nd = int64_t(c->n[0]) * c->n[1] * c->n[2];
+    if (nd > (int64_t(1) << 26)) return fail(RPA_EINVAL, "grid larger than 2^26 points");
+    if (int64_t(c->n[0]) * c->n[1] > 4096)
+        return fail(RPA_EINVAL, "x-y plane larger than 4096 points");
+    if (!(c->h > 0.0) || !std::isfinite(c->h)) return fail(RPA_EINVAL, "h must be finite and > 0");
+    if (c->n_occ < 1 || c->n_occ > 128 || c->n_occ >= nd)
+        return fail(RPA_EINVAL, "n_occ must be in [1, 128] and below N_d");
+    return RPA_OK;
+}
+
+int check_cell(const rpa_cell* c) {
+    RPA_CHECK(check_geometry(c));
+    if (!c->v_loc || !c->psi) return fail(RPA_EINVAL, "cell v_loc / psi pointer is NULL");
+    if (!c->eps) return fail(RPA_EINVAL, "cell eps (host) pointer is NULL");
+    for (int i = 0; i < c->n_occ; ++i) {
+        if (!std::isfinite(c->eps[i])) return fail(RPA_EINVAL, "eps has a non-finite value");
+        if (i > 0 && !(c->eps[i] > c->eps[i - 1]))
+            return fail(RPA_EINVAL, "eps must be strictly ascending");
+    }
+    return RPA_OK;
+}
+
+Grid grid_of(const rpa_cell* c) { return Grid{c->n[0], c->n[1], c->n[2], c->h}; }
+
+int check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return RPA_OK;
+    if (!ws) return fail(RPA_EWORKSPACE, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(RPA_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(RPA_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                        " bytes, got " + std::to_string(ws_bytes));
+    return RPA_OK;
+}
+
+// ------------------------------------------------------------------ buffer plans
+struct CoulombBuf {
+    double *Ux, *Uy, *Uz, *kx, *ky, *kz, *tmp;
+};
+void carve_coulomb(Carver& cv, const Grid& g, int nvec, CoulombBuf& b) {
+    b.Ux = cv.take<double>(size_t(g.n0) * g.n0);
+    b.Uy = cv.take<double>(size_t(g.n1) * g.n1);
+    b.Uz = cv.take<double>(size_t(g.n2) * g.n2);
+    b.kx = cv.take<double>(g.n0);
+    b.ky = cv.take<double>(g.n1);
+    b.kz = cv.take<double>(g.n2);
+    b.tmp = cv.take<double>(size_t(g.nd()) * nvec);
+}
+
+struct Chi0Buf {
+    int chunk;     // trial vectors per COCG launch
+    int nsplit;    // split-K of the coefficient GEMM
+    double* eps;
+    double* coeff;
+    double* part;
+    void *r, *pa, *pb, *x;
+    int *iters, *status;
+    double2* dbuf;  // backward only
+};
+
+int chunk_vectors(int ns, int nvec, const Opts& o) {
+    int ch = nvec;
+    if (o.max_systems > 0) ch = std::max(1, std::min(nvec, o.max_systems / ns));
+    return ch;
+}
+
+int coeff_split(int64_t nd, int ns, int S) {
+    const int tiles = ((ns + 63) / 64) * ((S + 63) / 64);
+    int sp = std::max(1, 1024 / std::max(1, tiles));
+    sp = int(std::min<int64_t>(sp, std::max<int64_t>(1, nd / 1024)));
+    return sp;
+}
+
+void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool x_complex,
+                bool with_d, Chi0Buf& b) {
+    b.chunk = chunk_vectors(ns, nvec, o);
+    const int S = ns * b.chunk;
+    const int64_t nd = g.nd();
+    b.nsplit = coeff_split(nd, ns, S);
+    const size_t cplx = (o.precision == RPA_MIXED) ? 8 : 16;
+    const size_t real = cplx / 2;
+    b.eps = cv.take<double>(ns);
+    b.coeff = cv.take<double>(size_t(ns) * S);
+    b.part = cv.take<double>(size_t(b.nsplit) * ns * S);
+    b.r = cv.take<char>(size_t(S) * nd * cplx);
+    b.pa = cv.take<char>(size_t(S) * nd * cplx);
+    b.pb = cv.take<char>(size_t(S) * nd * cplx);
+    b.x = cv.take<char>(size_t(S) * nd * (x_complex ? cplx : real));
+    b.iters = cv.take<int>(S);
+    b.status = cv.take<int>(S);
+    b.dbuf = with_d ? cv.take<double2>(size_t(ns) * S) : nullptr;
+}
+
+int gram_split(int64_t nd, int m) {
+    const int tiles = ((m + 63) / 64) * ((m + 63) / 64);
+    int sp = std::max(1, 512 / tiles);
+    return int(std::min<int64_t>(sp, std::max<int64_t>(1, nd / 512)));
+}
+
+struct SubBuf {
+    CoulombBuf cb;
+    Chi0Buf xb;
+    double *U, *D, *R, *C, *M, *L, *T, *part, *ework, *escal, *eigw, *eigwork;
+    int* info;
+    int gsplit;
+};
+void carve_sub(Carver& cv, const Grid& g, int ns, int nr, const Opts& o, SubBuf& b) {
+    carve_coulomb(cv, g, nr, b.cb);
+    carve_chi0(cv, g, ns, nr, o, false, false, b.xb);
+    const size_t blk = size_t(g.nd()) * nr, sq = size_t(nr) * nr;
+    b.U = cv.take<double>(blk);
+    b.D = cv.take<double>(blk);
+    b.R = cv.take<double>(blk);
+    b.C = cv.take<double>(sq);
+    b.M = cv.take<double>(sq);
+    b.L = cv.take<double>(sq);
+    b.T = cv.take<double>(sq);
+    b.gsplit = gram_split(g.nd(), nr);
+    b.part = cv.take<double>(size_t(b.gsplit) * sq);
+    b.ework = cv.take<double>(2 * sq);
+    b.escal = cv.take<double>(8);
+    b.eigw = cv.take<double>(nr);
+    b.eigwork = cv.take<double>(2 * sq);
+    b.info = cv.take<int>(8);
+}
+
+struct EnergyBuf {
+    SubBuf sb;
+    double *Vstart, *Vcur;
+};
+void carve_energy(Carver& cv, const Grid& g, int ns, int nr, const Opts& o, EnergyBuf& b) {
+    carve_sub(cv, g, ns, nr, o, b.sb);
+    b.Vstart = cv.take<double>(size_t(g.nd()) * nr);
+    b.Vcur = cv.take<double>(size_t(g.nd()) * nr);
+}
+
+struct BackBuf {
+    CoulombBuf cb;
+    Chi0Buf xb;
+    double *W, *U, *Y, *mu, *eigwork, *coefk;
+};
+void carve_back(Carver& cv, const Grid& g, int ns, int nr, const Opts& o, BackBuf& b) {
+    carve_coulomb(cv, g, nr, b.cb);
+    carve_chi0(cv, g, ns, nr, o, true, true, b.xb);
+    const size_t blk = size_t(g.nd()) * nr, sq = size_t(nr) * nr;
+    b.W = cv.take<double>(blk);
+    b.U = cv.take<double>(blk);
+    b.Y = cv.take<double>(sq);
+    b.mu = cv.take<double>(nr);
+    b.eigwork = cv.take<double>(2 * sq);
+    b.coefk = cv.take<double>(nr);
+}
+
+// ------------------------------------------------------------------ building blocks
+int coulomb_setup(const Grid& g, const CoulombBuf& b, hipStream_t s) {
+    RPA_HIP(launch_eigbasis_1d(g.n0, g.h, b.Ux, b.kx, s));
+    RPA_HIP(launch_eigbasis_1d(g.n1, g.h, b.Uy, b.ky, s));
+    RPA_HIP(launch_eigbasis_1d(g.n2, g.h, b.Uz, b.kz, s));
+    return RPA_OK;
+}
+
+int coulomb_apply(const Grid& g, const CoulombBuf& b, int power, int nvec, const double* in,
+                  double* out, hipStream_t s) {
+    RPA_HIP(launch_kron_apply(g, power, nvec, in, out, b.tmp, b.Ux, b.Uy, b.Uz, b.kx, b.ky, b.kz,
+                              s));
+    return RPA_OK;
+}
+
+struct SolveTally {
+    int64_t iters_total = 0, systems = 0;
+    int iters_max = 0, unconv = 0, breakdown = 0;
+};
+
+int tally(const Chi0Buf& b, int S, SolveTally& t, hipStream_t s) {
+    std::vector<int> it(S), st(S);
+    RPA_HIP(hipMemcpyAsync(it.data(), b.iters, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+    RPA_HIP(hipMemcpyAsync(st.data(), b.status, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+    RPA_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < S; ++i) {
+        t.iters_total += it[i];
+        t.iters_max = std::max(t.iters_max, it[i]);
+        t.unconv += (st[i] == 1);
+        t.breakdown += (st[i] == 2);
+    }
+    t.systems += S;
+    return RPA_OK;
+}
+
+void add_stats(rpa_stats* st, const SolveTally& t) {
+    if (!st) return;
+    st->cocg_iters_total += t.iters_total;
+    st->cocg_systems += t.systems;
+    st->cocg_iters_max = std::max<int32_t>(st->cocg_iters_max, t.iters_max);
+    st->n_unconverged += t.unconv;
+    st->n_breakdown += t.breakdown;
+}
+
+// Solve the Sternheimer systems of the trial vectors U[:, j0:j0+nv] at one frequency.
+int solve_chunk(const rpa_cell* cell, const Grid& g, double omega, const Opts& o,
+                const Chi0Buf& b, const double* U, int nv, bool x_complex, hipStream_t s) {
+    const int ns = cell->n_occ;
+    const int64_t nd = g.nd();
+    const double dV = g.h * g.h * g.h;
+    RPA_HIP(launch_proj_coeff(nd, ns, nv, dV, cell->psi, U, b.part, b.nsplit, b.coeff, s));
+    RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff,
+                                    reinterpret_cast<double*>(b.r), s));
+    CocgLaunch L{};
+    L.g = g;
+    L.nsys = ns * nv;
+    L.ns = ns;
+    L.vloc = cell->v_loc;
+    L.eps = b.eps;
+    L.omega = omega;
+    L.tol = o.cocg_tol;
+    L.max_iter = o.cocg_max_iter;
+    L.r = b.r;
+    L.pa = b.pa;
+    L.pb = b.pb;
+    L.x = b.x;
+    L.x_complex = x_complex;
+    L.iters = b.iters;
+    L.status = b.status;
+    L.fp32 = false;
+    RPA_HIP(launch_cocg(L, s));
+    return RPA_OK;
+}
+
+int chi0_apply(const rpa_cell* cell, const Grid& g, double omega, int nvec, const double* in,
+               double* out, const Opts& o, const Chi0Buf& b, SolveTally& t, hipStream_t s) {
+    const int ns = cell->n_occ;
+    const int64_t nd = g.nd();
+    RPA_HIP(hipMemcpyAsync(b.eps, cell->eps, sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    for (int j0 = 0; j0 < nvec; j0 += b.chunk) {
+        const int nv = std::min(b.chunk, nvec - j0);
+        RPA_CHECK(solve_chunk(cell, g, omega, o, b, in + nd * j0, nv, false, s));
+        RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
+                            out + nd * j0, s));
+        RPA_CHECK(tally(b, ns * nv, t, s));
+    }
+    return RPA_OK;
+}
+
+int solve_status(const SolveTally& t) {
+    if (t.breakdown) return fail(RPA_EBREAKDOWN, std::to_string(t.breakdown) +
+                                                     " COCG system(s) broke down");
+    if (t.unconv) {
+        set_error(std::to_string(t.unconv) + " COCG system(s) hit cocg_max_iter");
+        return RPA_ENOTCONV;
+    }
+    return RPA_OK;
+}
+
+// Orthonormalise R into V: M = R^T R = L L^T, V = R L^{-T}.
+int chol_orthonormalize(const Grid& g, int nr, const double* R, double* V, SubBuf& b,
+                        hipStream_t s) {
+    const int64_t nd = g.nd();
+    RPA_HIP(launch_gram(nd, nr, R, R, b.part, b.gsplit, b.M, s));
+    RPA_HIP(launch_chol_inv(nr, b.M, b.L, b.T, b.info, s));
+    int info = 0;
+    RPA_HIP(hipMemcpyAsync(&info, b.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    RPA_HIP(hipStreamSynchronize(s));
+    if (info != 0)
+        return fail(RPA_ENOTPD, "Cholesky of R^T R failed at column " + std::to_string(info));
+    RPA_HIP(launch_gemm_tall_small(nd, nr, R, b.T, V, s));
+    return RPA_OK;
+}
+
+struct SubResult {
+    double E = 0.0;
+    int n_iter = 0;
+};
+
+int subspace_iter(const rpa_cell* cell, const Grid& g, double omega, double weight, int nr,
+                  double* V, double* V_saved, double* C_out, double* ritz_out, const Opts& o,
+                  SubBuf& b, SolveTally& t, rpa_stats* stats, SubResult& res, hipStream_t s,
+                  bool coulomb_ready) {
+    const int64_t nd = g.nd();
+    if (!coulomb_ready) RPA_CHECK(coulomb_setup(g, b.cb, s));
+    double Eprev = 0.0, E = 0.0;
+    int k = 0;
+    for (;;) {
+        ++k;
+        RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, V, b.U, s));
+        RPA_CHECK(chi0_apply(cell, g, omega, nr, b.U, b.D, o, b.xb, t, s));
+        RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, b.D, b.R, s));
+        RPA_HIP(launch_gram(nd, nr, V, b.R, b.part, b.gsplit, b.C, s));
+        RPA_HIP(launch_symmetrize(nr, b.C, s));
+        RPA_HIP(launch_energy_logdet(nr, b.C, weight / (2.0 * M_PI), b.ework, b.escal, b.info, s));
+        int info = 0;
+        RPA_HIP(hipMemcpyAsync(&E, b.escal, sizeof(double), hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipMemcpyAsync(&info, b.info, sizeof(int), hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipStreamSynchronize(s));
+        if (stats) {
+            stats->chi0_applies += 1;
+            stats->subspace_iters_total += 1;
+        }
+        if (info != 0) return fail(RPA_ENOTPD, "I - C is not positive definite");
+        if (!std::isfinite(E)) return fail(RPA_EINVAL, "non-finite subspace energy");
+        if (V_saved) RPA_HIP(launch_copy(nd * nr, V, V_saved, s));
+        if (C_out) RPA_HIP(launch_copy(int64_t(nr) * nr, b.C, C_out, s));
+        RPA_CHECK(chol_orthonormalize(g, nr, b.R, V, b, s));
+        bool stop;
+        if (o.ec_tol <= 0.0) stop = (k >= o.subspace_iters);
+        else stop = (k >= o.subspace_iters) || (k >= 2 && std::fabs(E - Eprev) <= o.ec_tol * std::fabs(E));
+        Eprev = E;
+        if (stop) break;
+    }
+    if (ritz_out) {
+        // eigenvalues of the C behind the reported energy (still in b.C)
+        RPA_HIP(launch_syevj(nr, b.C, b.eigwork, b.eigw, nullptr, s));
+        RPA_HIP(hipMemcpyAsync(ritz_out, b.eigw, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipStreamSynchronize(s));
+    }
+    res.E = E;
+    res.n_iter = k;
+    return RPA_OK;
+}
+
+}  // namespace
+}  // namespace rpa
+
+using namespace rpa;
+
+extern "C" {
+
+int rpa_version(void) { return kVersion; }
+
+const char* rpa_error_string(int code) {
+    switch (code) {
+        case RPA_OK: return "ok";
+        case RPA_ENOTCONV: return "COCG did not converge within cocg_max_iter (results written)";
+        case RPA_EINVAL: return "invalid argument";
+        case RPA_EWORKSPACE: return "workspace missing, misaligned or too small";
+        case RPA_EBREAKDOWN: return "COCG breakdown";
+        case RPA_ENOTPD: return "matrix not positive definite";
+        case RPA_EHIP: return "HIP runtime error";
+        case RPA_ENOTIMPL: return "not implemented";
+        default: return "unknown status";
+    }
+}
+
+const char* rpa_last_error(void) { return g_last_error.c_str(); }
+
+int rpa_default_options(rpa_options* opt) {
+    if (!opt) return fail(RPA_EINVAL, "options pointer is NULL");
+    Opts d;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = d.precision;
+    opt->cocg_max_iter = d.cocg_max_iter;
+    opt->cocg_tol = d.cocg_tol;
+    opt->subspace_iters = d.subspace_iters;
+    opt->freq_mode = d.freq_mode;
+    opt->ec_tol = d.ec_tol;
+    opt->refine_tol = d.refine_tol;
+    opt->max_systems = d.max_systems;
+    opt->flags = 0;
+    return RPA_OK;
+}
+
+int rpa_workspace_size(int32_t op, int32_t ncell, const rpa_cell* cells, const int32_t* nvec,
+                       int32_t nfreq, const rpa_options* opt, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(RPA_EINVAL, "bytes pointer is NULL");
+    if (ncell < 1 || !cells || !nvec) return fail(RPA_EINVAL, "need ncell >= 1, cells and nvec");
+    if (op != RPA_OP_ENERGY && ncell != 1) return fail(RPA_EINVAL, "ncell must be 1 for this op");
+    Opts o;
+    RPA_CHECK(read_opts(opt, &o));
+    size_t need = 0;
+    for (int c = 0; c < ncell; ++c) {
+        RPA_CHECK(check_geometry(&cells[c]));
+        if (nvec[c] < 1 || nvec[c] > 65535) return fail(RPA_EINVAL, "nvec must be in [1, 65535]");
+        const Grid g = grid_of(&cells[c]);
+        const int ns = cells[c].n_occ;
+        Carver cv;
+        switch (op) {
+            case RPA_OP_COULOMB: { CoulombBuf b; carve_coulomb(cv, g, nvec[c], b); break; }
+            case RPA_OP_CHI0: { Chi0Buf b; carve_chi0(cv, g, ns, nvec[c], o, false, false, b); break; }
+            case RPA_OP_SUBSPACE: { SubBuf b; carve_sub(cv, g, ns, nvec[c], o, b); break; }
+            case RPA_OP_ENERGY: { EnergyBuf b; carve_energy(cv, g, ns, nvec[c], o, b); break; }
+            case RPA_OP_BACKWARD: {
+                if (nfreq < 1) return fail(RPA_EINVAL, "nfreq must be >= 1");
+                BackBuf b; carve_back(cv, g, ns, nvec[c], o, b); break;
+            }
+            default: return fail(RPA_EINVAL, "unknown op");
+        }
+        need = std::max(need, cv.used);
+    }
+    *bytes = need;
+    return RPA_OK;
+}
+
+int rpa_apply_coulomb(const rpa_cell* cell, int32_t power, int32_t nvec, const double* in,
+                      double* out, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    RPA_CHECK(check_geometry(cell));
+    if (power != 1 && power != 2) return fail(RPA_EINVAL, "power must be 1 or 2");
+    if (nvec < 1 || nvec > 65535) return fail(RPA_EINVAL, "nvec must be in [1, 65535]");
+    if (!in || !out) return fail(RPA_EINVAL, "in/out pointer is NULL");
+    const Grid g = grid_of(cell);
+    Carver dry;
+    CoulombBuf b;
+    carve_coulomb(dry, g, nvec, b);
+    RPA_CHECK(check_ws(ws, ws_bytes, dry.used));
+    Carver cv{static_cast<char*>(ws), 0};
+    carve_coulomb(cv, g, nvec, b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RPA_CHECK(coulomb_setup(g, b, s));
+    RPA_CHECK(coulomb_apply(g, b, power, nvec, in, out, s));
+    return RPA_OK;
+}
+
+int rpa_apply_chi0(const rpa_cell* cell, double omega, int32_t nvec, const double* in,
+                   double* out, const rpa_options* opt, rpa_stats* stats, void* ws,
+                   size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    RPA_CHECK(check_cell(cell));
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RPA_EINVAL, "omega must be > 0");
+    if (nvec < 1 || nvec > 65535) return fail(RPA_EINVAL, "nvec must be in [1, 65535]");
+    if (!in || !out) return fail(RPA_EINVAL, "in/out pointer is NULL");
+    if (in == out) return fail(RPA_EINVAL, "in and out must not overlap");
+    Opts o;
+    RPA_CHECK(read_opts(opt, &o));
+    const Grid g = grid_of(cell);
+    Carver dry;
+    Chi0Buf b;
+    carve_chi0(dry, g, cell->n_occ, nvec, o, false, false, b);
+    RPA_CHECK(check_ws(ws, ws_bytes, dry.used));
+    Carver cv{static_cast<char*>(ws), 0};
+    carve_chi0(cv, g, cell->n_occ, nvec, o, false, false, b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SolveTally t;
+    RPA_CHECK(chi0_apply(cell, g, omega, nvec, in, out, o, b, t, s));
+    add_stats(stats, t);
+    if (stats) stats->chi0_applies += 1;
+    return solve_status(t);
+}
+
+int rpa_subspace_iter(const rpa_cell* cell, double omega, double weight, int32_t nr, double* V,
+                      double* V_saved, double* C_out, double* ritz_out, double* ec_out,
+                      int32_t* n_iter, const rpa_options* opt, rpa_stats* stats, void* ws,
+                      size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    RPA_CHECK(check_cell(cell));
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RPA_EINVAL, "omega must be > 0");
+    if (!std::isfinite(weight)) return fail(RPA_EINVAL, "weight must be finite");
+    const Grid g = grid_of(cell);
+    if (nr < 1 || nr > 4096 || nr > g.nd()) return fail(RPA_EINVAL, "nr must be in [1, min(4096, N_d)]");
+    if (!V || !ec_out) return fail(RPA_EINVAL, "V and ec_out are required");
+    Opts o;
+    RPA_CHECK(read_opts(opt, &o));
+    Carver dry;
+    SubBuf b;
+    carve_sub(dry, g, cell->n_occ, nr, o, b);
+    RPA_CHECK(check_ws(ws, ws_bytes, dry.used));
+    Carver cv{static_cast<char*>(ws), 0};
+    carve_sub(cv, g, cell->n_occ, nr, o, b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SolveTally t;
+    SubResult res;
+    int rc = subspace_iter(cell, g, omega, weight, nr, V, V_saved, C_out, ritz_out, o, b, t, stats,
+                           res, s, false);
+    add_stats(stats, t);
+    if (rc < 0) return rc;
+    *ec_out = res.E;
+    if (n_iter) *n_iter = res.n_iter;
+    return solve_status(t);
+}
+
+int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t nfreq,
+               const double* omega, const double* weight, const double* const* V0,
+               double* const* Vsave, double* const* Csave, const rpa_options* opt,
+               double* ec_out, double* ec_freq_out, int32_t* iters_out, rpa_stats* stats,
+               void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    if (ncell < 1 || !cells || !nr || !V0 || !ec_out)
+        return fail(RPA_EINVAL, "need ncell >= 1, cells, nr, V0 and ec_out");
+    if (nfreq < 1 || !omega || !weight) return fail(RPA_EINVAL, "need nfreq >= 1, omega, weight");
+    for (int m = 0; m < nfreq; ++m) {
+        if (!(omega[m] > 0.0) || !std::isfinite(omega[m])) return fail(RPA_EINVAL, "omega must be > 0");
+        if (!std::isfinite(weight[m])) return fail(RPA_EINVAL, "weights must be finite");
+    }
+    Opts o;
+    RPA_CHECK(read_opts(opt, &o));
+    size_t need = 0;
+    for (int c = 0; c < ncell; ++c) {
+        RPA_CHECK(check_cell(&cells[c]));
+        const Grid g = grid_of(&cells[c]);
+        if (nr[c] < 1 || nr[c] > 4096 || nr[c] > g.nd())
+            return fail(RPA_EINVAL, "nr must be in [1, min(4096, N_d)]");
+        if (!V0[c]) return fail(RPA_EINVAL, "V0 pointer is NULL");
+        Carver dry;
+        EnergyBuf b;
+        carve_energy(dry, g, cells[c].n_occ, nr[c], o, b);
+        need = std::max(need, dry.used);
+    }
+    RPA_CHECK(check_ws(ws, ws_bytes, need));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SolveTally t;
+    for (int c = 0; c < ncell; ++c) {
+        const rpa_cell* cell = &cells[c];
+        const Grid g = grid_of(cell);
+        const int64_t nd = g.nd();
+        const int m_r = nr[c];
+        Carver cv{static_cast<char*>(ws), 0};
+        EnergyBuf b;
+        carve_energy(cv, g, cell->n_occ, m_r, o, b);
+        RPA_CHECK(coulomb_setup(g, b.sb.cb, s));
+        RPA_CHECK(chol_orthonormalize(g, m_r, V0[c], b.Vstart, b.sb, s));
+        RPA_HIP(launch_copy(nd * m_r, b.Vstart, b.Vcur, s));
+        double total = 0.0;
+        for (int m = 0; m < nfreq; ++m) {
+            if (o.freq_mode == RPA_INDEPENDENT && m > 0)
+                RPA_HIP(launch_copy(nd * m_r, b.Vstart, b.Vcur, s));
+            double* vs = (Vsave && Vsave[c]) ? Vsave[c] + size_t(m) * nd * m_r : nullptr;
+            double* csv = (Csave && Csave[c]) ? Csave[c] + size_t(m) * m_r * m_r : nullptr;
+            SubResult res;
+            int rc = subspace_iter(cell, g, omega[m], weight[m], m_r, b.Vcur, vs, csv, nullptr, o,
+                                   b.sb, t, stats, res, s, true);
+            if (rc < 0) {
+                add_stats(stats, t);
+                return rc;
+            }
+            total += res.E;
+            if (ec_freq_out) ec_freq_out[size_t(c) * nfreq + m] = res.E;
+            if (iters_out) iters_out[size_t(c) * nfreq + m] = res.n_iter;
+        }
+        ec_out[c] = total;
+    }
+    add_stats(stats, t);
+    return solve_status(t);
+}
+
+int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega,
+                        const double* weight, int32_t nr, const double* Vsave,
+                        const double* Csave, double grad_ec, double* grad_vloc,
+                        const rpa_options* opt, rpa_stats* stats, void* ws, size_t ws_bytes,
+                        void* stream) {
+    g_last_error.clear();
+    RPA_CHECK(check_cell(cell));
+    if (nfreq < 1 || !omega || !weight) return fail(RPA_EINVAL, "need nfreq >= 1, omega, weight");
+    for (int m = 0; m < nfreq; ++m) {
+        if (!(omega[m] > 0.0) || !std::isfinite(omega[m])) return fail(RPA_EINVAL, "omega must be > 0");
+        if (!std::isfinite(weight[m])) return fail(RPA_EINVAL, "weights must be finite");
+    }
+    const Grid g = grid_of(cell);
+    if (nr < 1 || nr > 4096 || nr > g.nd()) return fail(RPA_EINVAL, "nr must be in [1, min(4096, N_d)]");
+    if (!Vsave || !Csave || !grad_vloc) return fail(RPA_EINVAL, "Vsave, Csave, grad_vloc required");
+    if (!std::isfinite(grad_ec)) return fail(RPA_EINVAL, "grad_ec must be finite");
+    Opts o;
+    RPA_CHECK(read_opts(opt, &o));
+    Carver dry;
+    BackBuf b;
+    carve_back(dry, g, cell->n_occ, nr, o, b);
+    RPA_CHECK(check_ws(ws, ws_bytes, dry.used));
+    Carver cv{static_cast<char*>(ws), 0};
+    carve_back(cv, g, cell->n_occ, nr, o, b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int ns = cell->n_occ;
+    const int64_t nd = g.nd();
+    SolveTally t;
+    RPA_CHECK(coulomb_setup(g, b.cb, s));
+    RPA_HIP(hipMemcpyAsync(b.xb.eps, cell->eps, sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    RPA_HIP(launch_fill(nd, 0.0, grad_vloc, s));
+    std::vector<double> mu(nr), ck(nr);
+    for (int m = 0; m < nfreq; ++m) {
+        const double* Vm = Vsave + size_t(m) * nd * nr;
+        const double* Cm = Csave + size_t(m) * nr * nr;
+        RPA_HIP(launch_syevj(nr, Cm, b.eigwork, b.mu, b.Y, s));
+        RPA_HIP(hipMemcpyAsync(mu.data(), b.mu, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < nr; ++k) ck[k] = weight[m] / (2.0 * M_PI) * (-mu[k] / (1.0 - mu[k]));
+        RPA_HIP(hipMemcpyAsync(b.coefk, ck.data(), sizeof(double) * nr, hipMemcpyHostToDevice, s));
+        RPA_HIP(launch_gemm_tall_small(nd, nr, Vm, b.Y, b.W, s));
+        RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, b.W, b.U, s));
+        for (int j0 = 0; j0 < nr; j0 += b.xb.chunk) {
+            const int nv = std::min(b.xb.chunk, nr - j0);
+            RPA_CHECK(solve_chunk(cell, g, omega[m], o, b.xb, b.U + nd * j0, nv, true, s));
+            RPA_HIP(launch_grad_accum_d(nd, ns, nv, cell->psi, b.xb.eps, omega[m], b.xb.coeff,
+                                        b.xb.dbuf, b.coefk + j0, b.xb.x, false, grad_vloc, s));
+            RPA_CHECK(tally(b.xb, ns * nv, t, s));
+        }
+        if (stats) stats->chi0_applies += 1;
+    }
+    RPA_HIP(launch_scale(nd, grad_ec, grad_vloc, s));
+    RPA_HIP(hipStreamSynchronize(s));
+    add_stats(stats, t);
+    return solve_status(t);
+}
+
+}  // extern "C"

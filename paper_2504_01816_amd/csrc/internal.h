@@ -1,0 +1,143 @@
+// Internal declarations of the gfx950 RPA library: device helpers, kernel launchers and
+// the workspace carver.  Everything here is private to the shared library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/rpa.h"
+
+namespace rpa {
+
+// ------------------------------------------------------------------ error plumbing
+void set_error(const std::string& msg);
+
+struct Status {
+    int code = RPA_OK;
+};
+
+#define RPA_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::rpa::set_error(std::string("HIP error '") + hipGetErrorString(e_) +  \
+                             "' at " __FILE__ ":" + std::to_string(__LINE__));     \
+            return RPA_EHIP;                                                       \
+        }                                                                          \
+    } while (0)
+
+#define RPA_CHECK(rc)              \
+    do {                           \
+        int rc_ = (rc);            \
+        if (rc_ < 0) return rc_;   \
+    } while (0)
+
+// ------------------------------------------------------------------ workspace carver
+// Bump allocator over the caller's workspace.  With base == nullptr it only counts, so the
+// size query and the real carving run the same code and always agree.
+struct Carver {
+    char* base = nullptr;
+    size_t used = 0;
+    template <typename T>
+    T* take(size_t count) {
+        used = (used + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+// ------------------------------------------------------------------ grid geometry
+struct Grid {
+    int n0, n1, n2;
+    double h;
+    int64_t nd() const { return int64_t(n0) * n1 * n2; }
+};
+
+// 12th-order centred second-derivative weights w_0..w_6 (exact rationals, see fd_weights()).
+void fd_weights(double w[7]);
+
+// ------------------------------------------------------------------ kernel launchers
+// All launchers enqueue on `s` and return hipError_t of the launch.
+
+// Kronecker nu^{power/2}: 1D eigenbases (basis[3] device, n_a*n_a each, kappa[3] device n_a)
+hipError_t launch_eigbasis_1d(int n, double h, double* U, double* kappa, hipStream_t s);
+hipError_t launch_kron_apply(const Grid& g, int power, int nvec, const double* in, double* out,
+                             double* tmp, const double* Ux, const double* Uy, const double* Uz,
+                             const double* kx, const double* ky, const double* kz,
+                             hipStream_t s);
+
+// Occupied projector: coeff[l + ns*s] = dV sum_r psi[r,l] psi[r,n(s)] u[r,j(s)],
+// s = n + ns*j, for j in [0, nvec).  part: split-K partial buffer (nsplit*ns*ns*nvec).
+hipError_t launch_proj_coeff(int64_t nd, int ns, int nvec, double dV, const double* psi,
+                             const double* U, double* part, int nsplit, double* coeff,
+                             hipStream_t s);
+// r0[s][r] = -(psi[r,n] u[r,j] - sum_l psi[r,l] coeff[l,s]) written as complex (T = float or
+// double) with zero imaginary part.
+template <typename T>
+hipError_t launch_proj_rhs(int64_t nd, int ns, int nvec, const double* psi, const double* U,
+                           const double* coeff, T* r0, hipStream_t s);
+
+// Batched COCG, one workgroup per system.  See cocg.hip for the layout.
+struct CocgLaunch {
+    Grid g;
+    int nsys;              // systems in this launch
+    int ns;                // orbitals (system s uses eps[s % ns])
+    const double* vloc;    // N_d
+    const double* eps;     // device, ns
+    double omega;
+    double tol;
+    int max_iter;
+    void* r;               // nsys x N_d complex (T2)
+    void* pa;              // nsys x N_d complex
+    void* pb;              // nsys x N_d complex
+    void* x;               // nsys x N_d real (or complex if x_complex)
+    bool x_complex;
+    int* iters;            // nsys
+    int* status;           // nsys (0 ok, 1 not converged, 2 breakdown)
+    bool fp32;             // state in complex64
+};
+hipError_t launch_cocg(const CocgLaunch& a, hipStream_t s);
+
+// Delta rho epilogue: out[r, j] = 4 sum_n psi[r,n] xre[n + ns*j][r]
+hipError_t launch_drho(int64_t nd, int ns, int nvec, const double* psi, const double* xre,
+                       double* out, hipStream_t s);
+
+// Dense FP64 helpers on small N_r x N_r matrices and tall N_d x N_r blocks.
+// G = A^T B (A: nd x m, B: nd x m, both column-major), G: m x m column-major; split-K.
+hipError_t launch_gram(int64_t nd, int m, const double* A, const double* B, double* part,
+                       int nsplit, double* G, hipStream_t s);
+// Y = A * T (A: nd x m, T: m x m), Y may not alias A.
+hipError_t launch_gemm_tall_small(int64_t nd, int m, const double* A, const double* T,
+                                  double* Y, hipStream_t s);
+// Symmetrise C <- (C + C^T)/2 (in place).
+hipError_t launch_symmetrize(int m, double* C, hipStream_t s);
+// Lower Cholesky of M (in place into L, upper part zeroed) then T = L^{-T} (upper).
+// info[0] = 0 on success, k+1 if the k-th pivot is not positive.
+hipError_t launch_chol_inv(int m, const double* M, double* L, double* T, int* info,
+                           hipStream_t s);
+// E = scale * (ln det(I - C) + tr C) via Cholesky of I - C; out[0] = E, info[0] as above.
+hipError_t launch_energy_logdet(int m, const double* C, double scale, double* work,
+                                double* out, int* info, hipStream_t s);
+// Symmetric eigen-decomposition by cyclic Jacobi: A (m x m) copied to work; eigenvalues
+// ascending into w, eigenvectors (columns) into Y if Y != nullptr.
+hipError_t launch_syevj(int m, const double* A, double* work, double* w, double* Y,
+                        hipStream_t s);
+
+// Gradient epilogue for one block of systems (s = n + ns k):
+// grad[r] += sum_s coefk[k] * 4 Re[(x_s + o_s)(r) x_s(r)],
+// o_s = -sum_l psi[r,l] d[l,s],  d[l,s] = coeff[l,s] / (eps_l - eps_n - i omega) (into dbuf)
+hipError_t launch_grad_accum_d(int64_t nd, int ns, int nvec, const double* psi,
+                               const double* eps, double omega, const double* coeff,
+                               double2* dbuf, const double* coefk, const void* x, bool x_fp32,
+                               double* grad, hipStream_t s);
+hipError_t launch_drho_f32(int64_t nd, int ns, int nvec, const double* psi, const float* xre,
+                           double* out, hipStream_t s);
+hipError_t launch_scale(int64_t n, double a, double* x, hipStream_t s);
+hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t s);
+hipError_t launch_fill(int64_t n, double v, double* x, hipStream_t s);
+
+}  // namespace rpa

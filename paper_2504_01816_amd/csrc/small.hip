@@ -1,0 +1,355 @@
+// Small dense FP64 kernels of the subspace step (Algorithm 1) and the pointwise epilogues.
+//  * Cholesky of the N_r x N_r overlap M = R^T R and T = L^{-T}, so V = R T (orthonormalisation)
+//  * E_{c,m} = W/(2 pi) sum_k g(mu_k) through sum_k g(mu_k) = ln det(I - C) + tr C, with
+//    I - C symmetric positive definite because C <= 0 (Eq. 10)
+//  * cyclic Jacobi eigensolver for the Ritz values and vectors of C (Rayleigh-Ritz)
+//  * Delta rho = 4 sum_n psi_n Re(x_n) (Eq. 8) and the gradient accumulation
+// Each small-matrix kernel runs as one workgroup of 1024 threads on a matrix that stays in
+// L2; N_r is at most a few hundred, so these are latency-bound and a small share of a
+// subspace iteration.
+#include "internal.h"
+
+namespace rpa {
+namespace {
+
+constexpr int SB = 1024;
+
+__device__ double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// Lower Cholesky factor of the m x m column-major matrix A into L (upper part zeroed),
+// left-looking, one column per step.  Returns through info: 0 or (failing column + 1).
+__device__ void chol_block(int m, const double* A, double* L, int* info, double* rowj,
+                           int* sflag) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int i = tid; i < m * m; i += bs) {
+        const int r = i % m, c = i / m;
+        L[i] = (r >= c) ? A[i] : 0.0;
+    }
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        for (int k = tid; k < j; k += bs) rowj[k] = L[j + int64_t(m) * k];
+        __syncthreads();
+        for (int i = j + tid; i < m; i += bs) {
+            double s = L[i + int64_t(m) * j];
+            for (int k = 0; k < j; ++k) s -= L[i + int64_t(m) * k] * rowj[k];
+            L[i + int64_t(m) * j] = s;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double d = L[j + int64_t(m) * j];
+            if (!(d > 0.0) && *sflag == 0) *sflag = j + 1;
+            L[j + int64_t(m) * j] = (d > 0.0) ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double piv = L[j + int64_t(m) * j];
+        for (int i = j + 1 + tid; i < m; i += bs) L[i + int64_t(m) * j] /= piv;
+        __syncthreads();
+    }
+    if (tid == 0) *info = *sflag;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(SB) void chol_inv_kernel(int m, const double* M, double* L,
+                                                      double* T, int* info) {
+    extern __shared__ double sh[];
+    __shared__ int sflag;
+    chol_block(m, M, L, info, sh, &sflag);
+    // T = (L^{-1})^T: thread c solves L x = e_c by forward substitution, x_i = T[c + m i]
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+        for (int i = 0; i < c; ++i) T[c + int64_t(m) * i] = 0.0;
+        for (int i = c; i < m; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) s -= L[i + int64_t(m) * k] * T[c + int64_t(m) * k];
+            T[c + int64_t(m) * i] = s / L[i + int64_t(m) * i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(SB) void energy_kernel(int m, const double* C, double scale,
+                                                    double* work, double* out, int* info) {
+    extern __shared__ double sh[];
+    __shared__ int sflag;
+    __shared__ double red[SB / 64];
+    double* B = work;                 // I - C
+    double* L = work + int64_t(m) * m;
+    for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+        const int r = i % m, c = i / m;
+        B[i] = (r == c ? 1.0 : 0.0) - C[i];
+    }
+    __syncthreads();
+    chol_block(m, B, L, info, sh, &sflag);
+    double v = 0.0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x)
+        v += 2.0 * log(L[i + int64_t(m) * i]) + C[i + int64_t(m) * i];
+    const double s = block_sum(v, red);
+    if (threadIdx.x == 0) out[0] = scale * s;
+}
+
+__global__ void symmetrize_kernel(int m, double* C) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m * m) return;
+    const int r = i % m, c = i / m;
+    if (r < c) {
+        const double a = C[r + int64_t(m) * c], b = C[c + int64_t(m) * r];
+        const double s = 0.5 * (a + b);
+        C[r + int64_t(m) * c] = s;
+        C[c + int64_t(m) * r] = s;
+    }
+}
+
+// Cyclic Jacobi with the round-robin ordering: each step rotates m/2 disjoint pairs at once.
+__global__ __launch_bounds__(SB) void syevj_kernel(int m, const double* Ain, double* work,
+                                                   double* w, double* Yout) {
+    extern __shared__ double sh[];  // cs[2 * mm/2] then diag copy
+    __shared__ double red[SB / 64];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int mm = m + (m & 1);
+    const int np = mm / 2;
+    double* A = work;
+    double* Y = work + int64_t(m) * m;
+    double* cs = sh;                 // 2*np
+    int* pp = reinterpret_cast<int*>(sh + 2 * np);  // 2*np ints
+    for (int i = tid; i < m * m; i += bs) {
+        A[i] = 0.5 * (Ain[i] + Ain[(i / m) + int64_t(m) * (i % m)]);
+        Y[i] = (i % m == i / m) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double fro = 0.0;
+    for (int i = tid; i < m * m; i += bs) fro += A[i] * A[i];
+    fro = block_sum(fro, red);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int i = tid; i < m * m; i += bs)
+            if (i % m != i / m) off += A[i] * A[i];
+        off = block_sum(off, red);
+        if (!(off > 1e-30 * fro) || fro == 0.0) break;
+        for (int t = 0; t < mm - 1; ++t) {
+            for (int k = tid; k < np; k += bs) {
+                const int a0 = (k == 0) ? 0 : ((k - 1 + t) % (mm - 1)) + 1;
+                const int k2 = mm - 1 - k;
+                const int b0 = ((k2 - 1 + t) % (mm - 1)) + 1;
+                int p = min(a0, b0), q = max(a0, b0);
+                double c = 1.0, s = 0.0;
+                if (q < m) {
+                    const double apq = A[p + int64_t(m) * q];
+                    if (apq != 0.0) {
+                        const double app = A[p + int64_t(m) * p], aqq = A[q + int64_t(m) * q];
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                    }
+                } else {
+                    p = q = -1;
+                }
+                cs[2 * k] = c;
+                cs[2 * k + 1] = s;
+                pp[2 * k] = p;
+                pp[2 * k + 1] = q;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int it = tid; it < np * m; it += bs) {
+                const int k = it / m, col = it % m;
+                const int p = pp[2 * k], q = pp[2 * k + 1];
+                if (p < 0) continue;
+                const double c = cs[2 * k], s = cs[2 * k + 1];
+                const double ap = A[p + int64_t(m) * col], aq = A[q + int64_t(m) * col];
+                A[p + int64_t(m) * col] = c * ap - s * aq;
+                A[q + int64_t(m) * col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, Y <- Y J
+            for (int it = tid; it < np * m; it += bs) {
+                const int k = it / m, row = it % m;
+                const int p = pp[2 * k], q = pp[2 * k + 1];
+                if (p < 0) continue;
+                const double c = cs[2 * k], s = cs[2 * k + 1];
+                double ap = A[row + int64_t(m) * p], aq = A[row + int64_t(m) * q];
+                A[row + int64_t(m) * p] = c * ap - s * aq;
+                A[row + int64_t(m) * q] = s * ap + c * aq;
+                ap = Y[row + int64_t(m) * p];
+                aq = Y[row + int64_t(m) * q];
+                Y[row + int64_t(m) * p] = c * ap - s * aq;
+                Y[row + int64_t(m) * q] = s * ap + c * aq;
+            }
+            __syncthreads();
+        }
+    }
+    // sort ascending (stable by index)
+    for (int i = tid; i < m; i += bs) {
+        const double di = A[i + int64_t(m) * i];
+        int rank = 0;
+        for (int j = 0; j < m; ++j) {
+            const double dj = A[j + int64_t(m) * j];
+            rank += (dj < di) || (dj == di && j < i);
+        }
+        w[rank] = di;
+        if (Yout)
+            for (int r = 0; r < m; ++r) Yout[r + int64_t(m) * rank] = Y[r + int64_t(m) * i];
+    }
+}
+
+template <typename X>
+__global__ void drho_kernel(int64_t nd, int ns, const double* psi, const X* xre, double* out) {
+    const int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int j = blockIdx.y;
+    if (r >= nd) return;
+    double s = 0.0;
+    for (int n = 0; n < ns; ++n)
+        s += psi[r + nd * n] * double(xre[(int64_t(n) + int64_t(ns) * j) * nd + r]);
+    out[r + nd * j] = 4.0 * s;
+}
+
+// d[l, s] = coeff[l, s] / (eps_l - eps_n - i omega), s = n + ns k
+__global__ void grad_d_kernel(int ns, int S, const double* eps, double omega, const double* coeff,
+                              double2* d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns * S) return;
+    const int l = i % ns, s = i / ns, n = s % ns;
+    const double a = eps[l] - eps[n], b = -omega;   // denominator a + i b
+    const double den = a * a + b * b;
+    const double c = coeff[i];
+    d[i] = double2{c * a / den, -c * b / den};
+}
+
+template <typename T2, int NSMAX>
+__global__ void grad_kernel(int64_t nd, int ns, int nvec, const double* psi, const double2* d,
+                            const double* coefk, const T2* x, double* grad) {
+    const int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (r >= nd) return;
+    double pr[NSMAX];
+#pragma unroll
+    for (int l = 0; l < NSMAX; ++l) pr[l] = (l < ns) ? psi[r + nd * l] : 0.0;
+    double acc = 0.0;
+    for (int k = 0; k < nvec; ++k) {
+        double ak = 0.0;
+        for (int n = 0; n < ns; ++n) {
+            const int s = n + ns * k;
+            double ore = 0.0, oim = 0.0;
+#pragma unroll
+            for (int l = 0; l < NSMAX; ++l) {
+                if (l < ns) {
+                    const double2 dl = d[l + int64_t(ns) * s];
+                    ore -= pr[l] * dl.x;
+                    oim -= pr[l] * dl.y;
+                }
+            }
+            const T2 xv = x[int64_t(s) * nd + r];
+            const double xr = double(xv.x), xi = double(xv.y);
+            // Re[(x + o) x]
+            ak += (xr + ore) * xr - (xi + oim) * xi;
+        }
+        acc += coefk[k] * 4.0 * ak;
+    }
+    grad[r] += acc;
+}
+
+__global__ void scale_kernel(int64_t n, double a, double* x) {
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < n) x[i] *= a;
+}
+__global__ void fill_kernel(int64_t n, double v, double* x) {
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+__global__ void copy_kernel(int64_t n, const double* src, double* dst) {
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+}  // namespace
+
+hipError_t launch_symmetrize(int m, double* C, hipStream_t s) {
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, m, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_inv(int m, const double* M, double* L, double* T, int* info,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(SB), size_t(m) * sizeof(double), s, m, M,
+                       L, T, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_logdet(int m, const double* C, double scale, double* work,
+                                double* out, int* info, hipStream_t s) {
+    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(SB), size_t(m) * sizeof(double), s, m, C,
+                       scale, work, out, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_syevj(int m, const double* A, double* work, double* w, double* Y,
+                        hipStream_t s) {
+    const int np = (m + 1) / 2;
+    const size_t sh = size_t(2 * np) * sizeof(double) + size_t(2 * np) * sizeof(int);
+    hipLaunchKernelGGL(syevj_kernel, dim3(1), dim3(SB), sh, s, m, A, work, w, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_drho(int64_t nd, int ns, int nvec, const double* psi, const double* xre,
+                       double* out, hipStream_t s) {
+    hipLaunchKernelGGL(drho_kernel<double>, dim3(unsigned((nd + 255) / 256), nvec), dim3(256), 0,
+                       s, nd, ns, psi, xre, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_drho_f32(int64_t nd, int ns, int nvec, const double* psi, const float* xre,
+                           double* out, hipStream_t s) {
+    hipLaunchKernelGGL(drho_kernel<float>, dim3(unsigned((nd + 255) / 256), nvec), dim3(256), 0,
+                       s, nd, ns, psi, xre, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_accum_d(int64_t nd, int ns, int nvec, const double* psi,
+                               const double* eps, double omega, const double* coeff,
+                               double2* dbuf, const double* coefk, const void* x, bool x_fp32,
+                               double* grad, hipStream_t s) {
+    const int S = ns * nvec;
+    hipLaunchKernelGGL(grad_d_kernel, dim3((ns * S + 255) / 256), dim3(256), 0, s, ns, S, eps,
+                       omega, coeff, dbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid(unsigned((nd + 127) / 128)), block(128);
+#define RPA_G(NSM)                                                                           \
+    if (ns <= NSM) {                                                                         \
+        if (x_fp32)                                                                          \
+            hipLaunchKernelGGL((grad_kernel<float2, NSM>), grid, block, 0, s, nd, ns, nvec,  \
+                               psi, dbuf, coefk, reinterpret_cast<const float2*>(x), grad);  \
+        else                                                                                 \
+            hipLaunchKernelGGL((grad_kernel<double2, NSM>), grid, block, 0, s, nd, ns, nvec, \
+                               psi, dbuf, coefk, reinterpret_cast<const double2*>(x), grad); \
+        return hipGetLastError();                                                            \
+    }
+    RPA_G(8) RPA_G(16) RPA_G(32) RPA_G(64) RPA_G(128)
+#undef RPA_G
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scale(int64_t n, double a, double* x, hipStream_t s) {
+    hipLaunchKernelGGL(scale_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, a, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t n, double v, double* x, hipStream_t s) {
+    hipLaunchKernelGGL(fill_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, v, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace rpa

@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry point,
+and validates arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2504_01816_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def so():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("library not built")
+    return L.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rpa.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpa_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(so):
+    names = declared_functions()
+    assert {"rpa_apply_chi0", "rpa_apply_coulomb", "rpa_subspace_iter", "rpa_energy",
+            "rpa_energy_backward", "rpa_workspace_size"} <= set(names)
+    for n in names:
+        assert hasattr(so, n), n
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(L.RpaCell) == 48
+    assert ctypes.sizeof(L.RpaOptions) == 48
+    assert ctypes.sizeof(L.RpaStats) == 40
+
+
+def _cell(n=(12, 12, 12), n_occ=4, h=0.5, eps=None):
+    c = L.RpaCell()
+    c.n[0], c.n[1], c.n[2] = n
+    c.n_occ = n_occ
+    c.h = h
+    c.v_loc = 0x1000
+    c.psi = 0x2000
+    e = np.arange(n_occ, dtype=np.float64) if eps is None else np.asarray(eps, dtype=np.float64)
+    c._keep = e
+    c.eps = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return c
+
+
+def test_defaults_and_error_strings(so):
+    o = L.default_options()
+    assert o.precision == L.RPA_FP64 and o.cocg_tol == 1e-8 and o.freq_mode == L.RPA_WARM
+    assert so.rpa_version() >= 10000
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert so.rpa_error_string(code)
+
+
+def test_workspace_query_is_host_only_and_monotone(so):
+    c = _cell()
+    sizes = []
+    for nvec in (1, 4, 16):
+        out = ctypes.c_size_t(0)
+        nv = (ctypes.c_int32 * 1)(nvec)
+        rc = so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(c), nv, 1, None, ctypes.byref(out))
+        assert rc == 0
+        sizes.append(out.value)
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    # the chi0 state is at least x, r, two p buffers per system: (8 + 3*16) B per point
+    assert sizes[2] >= 16 * 4 * 12 ** 3 * 56
+    # capping systems in flight lowers the workspace
+    o = L.default_options(max_systems=8)
+    out = ctypes.c_size_t(0)
+    nv = (ctypes.c_int32 * 1)(16)
+    assert so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(c), nv, 1, ctypes.byref(o),
+                                 ctypes.byref(out)) == 0
+    assert out.value < sizes[2]
+
+
+@pytest.mark.parametrize("mut,code", [
+    (lambda c: setattr(c, "h", -1.0), L.RPA_EINVAL),
+    (lambda c: setattr(c, "n_occ", 0), L.RPA_EINVAL),
+    (lambda c: c.n.__setitem__(2, 8), L.RPA_EINVAL),       # marching axis needs >= 12
+    (lambda c: setattr(c, "v_loc", None), L.RPA_EINVAL),
+])
+def test_chi0_rejects_bad_cells(so, mut, code):
+    c = _cell()
+    mut(c)
+    rc = so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5000, 1 << 30,
+                           None)
+    assert rc == code
+    assert so.rpa_last_error()
+
+
+def test_chi0_rejects_bad_scalars_and_workspace(so):
+    c = _cell(eps=[0.0, 1.0, 0.5, 2.0])                     # not ascending
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5000, 1 << 30,
+                             None) == L.RPA_EINVAL
+    c = _cell()
+    assert so.rpa_apply_chi0(ctypes.byref(c), 0.0, 4, 0x3000, 0x4000, None, None, 0x5000, 1 << 30,
+                             None) == L.RPA_EINVAL           # omega must be > 0
+    assert so.rpa_apply_chi0(ctypes.byref(c), float("nan"), 4, 0x3000, 0x4000, None, None, 0x5000,
+                             1 << 30, None) == L.RPA_EINVAL
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x3000, None, None, 0x5000, 1 << 30,
+                             None) == L.RPA_EINVAL           # in == out
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, None, 0,
+                             None) == L.RPA_EWORKSPACE
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5010, 1 << 30,
+                             None) == L.RPA_EWORKSPACE       # misaligned
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5000, 1024,
+                             None) == L.RPA_EWORKSPACE       # too small
+    o = L.default_options(cocg_tol=0.0)
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(o), None,
+                             0x5000, 1 << 30, None) == L.RPA_EINVAL
+    o = L.default_options(freq_mode=7)
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(o), None,
+                             0x5000, 1 << 30, None) == L.RPA_EINVAL
+
+
+def test_energy_and_backward_validation(so):
+    c = _cell()
+    nr = (ctypes.c_int32 * 1)(8)
+    om = (ctypes.c_double * 2)(2.0, -1.0)
+    wt = (ctypes.c_double * 2)(1.0, 1.0)
+    v0 = (ctypes.c_void_p * 1)(0x6000)
+    ec = (ctypes.c_double * 1)()
+    rc = so.rpa_energy(1, ctypes.byref(c), nr, 2, om, wt, v0, None, None, None, ec, None, None,
+                       None, 0x5000, 1 << 30, None)
+    assert rc == L.RPA_EINVAL                                # negative frequency
+    rc = so.rpa_energy_backward(ctypes.byref(c), 1, om, wt, 8, None, None, 1.0, None, None, None,
+                                0x5000, 1 << 30, None)
+    assert rc == L.RPA_EINVAL                                # missing saved subspaces
+    rc = so.rpa_apply_coulomb(ctypes.byref(c), 3, 1, 0x3000, 0x4000, 0x5000, 1 << 30, None)
+    assert rc == L.RPA_EINVAL                                # power must be 1 or 2
