@@ -1,0 +1,181 @@
+"""Benchmark of the RPA chi0 hot path on one MI355X.
+
+A step is one pass of the whole hot path on the 24^3 workload (16 Gaussian wells,
+N_s = 16, N_r = 64, 8 Gauss-Legendre frequencies, COCG tol 1e-8): rpa_energy over all
+frequencies (subspace iteration from the highest frequency to the lowest, warm starts,
+stopping at a relative energy change of 1e-8, at most 50 iterations per frequency) and
+then rpa_energy_backward (one chi0 block-apply per frequency).  Inputs are synthetic,
+seeded and resident in HBM before the timed region.
+
+Printed: one JSON line with the metric (chi0 block-applies per second over the timed
+steps), time-to-E_c, the roofline of the dominant kernel (batched COCG) measured with
+HIP events on its own stream, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per grid point per COCG iteration: read and write x, r, p
+ALG_BYTES = {"fp64": 96.0, "mixed": 48.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1, help="workload index (0..4)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ec-tol", type=float, default=1e-8)
+    ap.add_argument("--max-subspace", type=int, default=50)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl):
+    """Oracle (as written, single BLAS thread) on one trial vector at three frequencies."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import chi0 as ochi0
+    from oracle import coulomb as ocoul
+
+    c = wl.cells[0]
+    nr = wl.n_r[0]
+    pick = [0, len(wl.omegas) // 2, len(wl.omegas) - 1]
+    V = wl.V0[0][:1].T.copy()
+    times = []
+    with threadpool_limits(1):
+        for m in pick:
+            t0 = time.perf_counter()
+            U = ocoul.nu_apply(V, c.shape, c.h, 1)
+            D, _, _ = ochi0.chi0_apply(U, c.vloc, c.psi.T, c.eps, float(wl.omegas[m]), c.shape, c.h,
+                                       wl.cocg_tol, 5000)
+            ocoul.nu_apply(D, c.shape, c.h, 1)
+            times.append(time.perf_counter() - t0)
+    per_apply = nr * float(np.mean(times))
+    return {"value": 1.0 / per_apply, "unit": "chi0 block-applies/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "1 of %d trial vectors (%d of %d Sternheimer systems) at omega = %s; "
+                      "block-apply time = %d x mean per-vector time %.2f s"
+                      % (nr, c.n_occ, c.n_occ * nr,
+                         ", ".join("%.4g" % wl.omegas[m] for m in pick), nr, float(np.mean(times)))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only; --gpus %d is not supported (multi-GPU sharding "
+              "is a design note, not part of this build)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2504_01816_amd import api, synth
+    from paper_2504_01816_amd import lib as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    wl = synth.workload(args.config)
+    print("[bench] workload %s generated in %.1f s" % (wl.name, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    cells = [api.device_cell(c, dev) for c in wl.cells]
+    V0 = [torch.tensor(v, device=dev) for v in wl.V0]
+    prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
+    opts = dict(precision=prec, cocg_tol=wl.cocg_tol, subspace_iters=args.max_subspace,
+                ec_tol=args.ec_tol, freq_mode=L.RPA_WARM)
+    if wl.subspace_iters > 0:
+        opts.update(subspace_iters=wl.subspace_iters, ec_tol=0.0)
+
+    def step():
+        st = {"fwd_s": 0.0, "bwd_s": 0.0, "applies": 0, "cocg_ms": 0.0, "point_iters": 0.0,
+              "launches": 0, "iters": None, "E": None}
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        res = api.rpa_energy(cells, wl.n_r, wl.omegas, wl.weights, V0, opts,
+                             save=not args.no_backward)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        st["fwd_s"] = b - a
+        for k in ("chi0_applies",):
+            st["applies"] += res["stats"][k]
+        st["cocg_ms"] += res["stats"]["cocg_kernel_ms"]
+        st["point_iters"] += res["stats"]["cocg_point_iters"]
+        st["launches"] += res["stats"]["cocg_launches"]
+        st["iters"] = res["iters"].tolist()
+        st["E"] = res["E_c"].tolist()
+        if not args.no_backward:
+            for ci, c in enumerate(cells):
+                g, rc, s2 = api.rpa_energy_backward(c, wl.omegas, wl.weights, res["Vsave"][ci],
+                                                    res["Csave"][ci], 1.0, opts)
+                st["applies"] += s2["chi0_applies"]
+                st["cocg_ms"] += s2["cocg_kernel_ms"]
+                st["point_iters"] += s2["cocg_point_iters"]
+                st["launches"] += s2["cocg_launches"]
+            torch.cuda.synchronize()
+            st["bwd_s"] = time.perf_counter() - b
+        return st
+
+    for w in range(args.warmup):
+        s = step()
+        print("[bench] warmup %d: %.2f s fwd, %.2f s bwd, subspace iters %s" %
+              (w, s["fwd_s"], s["bwd_s"], s["iters"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T0 = time.perf_counter()
+    steps = []
+    for k in range(args.steps):
+        s = step()
+        steps.append(s)
+        print("[bench] step %d: %.2f s fwd, %.2f s bwd, applies %d, E_c %s" %
+              (k, s["fwd_s"], s["bwd_s"], s["applies"], s["E"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - T0
+    applies = sum(s["applies"] for s in steps)
+    cocg_ms = sum(s["cocg_ms"] for s in steps)
+    pit = sum(s["point_iters"] for s in steps)
+    launches = sum(s["launches"] for s in steps)
+    alg = ALG_BYTES[args.precision] * pit
+    achieved = alg / (cocg_ms * 1e-3) / 1e9 if cocg_ms > 0 else 0.0
+    out = {
+        "metric": "chi0 block-applies/s and time-to-E_c, FP32-refined batched vs FP64, 1 GPU",
+        "value": applies / T,
+        "unit": "chi0 block-applies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128" if args.precision == "fp64" else "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.cells[0].shape), "h": wl.cells[0].h,
+                   "n_occ": wl.cells[0].n_occ, "n_r": wl.n_r[0], "n_freq": len(wl.omegas),
+                   "cocg_tol": wl.cocg_tol, "ec_tol": opts["ec_tol"],
+                   "backward": not args.no_backward, "precision": args.precision},
+        "time_to_ec_s": float(np.mean([s["fwd_s"] for s in steps])),
+        "backward_s": float(np.mean([s["bwd_s"] for s in steps])),
+        "E_c": steps[-1]["E"],
+        "subspace_iters": steps[-1]["iters"],
+        "chi0_applies_per_step": applies / args.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "cocg_wg (batched COCG, one workgroup per system)",
+                     "launches": launches, "avg_launch_ms": cocg_ms / max(1, launches),
+                     "alg_bytes_per_point_iter": ALG_BYTES[args.precision],
+                     "cocg_share_of_step": cocg_ms * 1e-3 / T},
+    }
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(wl)
+        print("[bench] cpu baseline %.1f s" % (time.perf_counter() - t), file=sys.stderr,
+              flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

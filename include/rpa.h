@@ -103,6 +103,10 @@ typedef struct rpa_stats {
     int32_t refinements;          /* float64 residual refinements (RPA_MIXED) */
     int32_t chi0_applies;         /* chi0 block-applies (one per subspace iteration) */
     int32_t subspace_iters_total; /* subspace iterations over all frequencies and cells */
+    int64_t cocg_launches;        /* launches of the batched COCG kernel */
+    double cocg_kernel_ms;        /* their summed duration, from HIP events recorded on the
+                                     stream of each launch */
+    double cocg_point_iters;      /* sum over systems of (COCG iterations x N_d) */
 } rpa_stats;
 
 /* Library version (major*10000 + minor*100 + patch). */

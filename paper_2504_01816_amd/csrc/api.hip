@@ -258,16 +258,44 @@ int coulomb_apply(const Grid& g, const CoulombBuf& b, int power, int nvec, const
 }
 
 struct SolveTally {
-    int64_t iters_total = 0, systems = 0;
+    int64_t iters_total = 0, systems = 0, launches = 0;
     int iters_max = 0, unconv = 0, breakdown = 0;
+    double kernel_ms = 0.0, point_iters = 0.0;
 };
 
-int tally(const Chi0Buf& b, int S, SolveTally& t, hipStream_t s) {
+// Events bracketing the COCG launches, created once per thread and device.
+struct CocgTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+    int device = -1;
+};
+static thread_local CocgTimer g_timer;
+
+int timer_events(hipEvent_t* a, hipEvent_t* b) {
+    int dev = 0;
+    RPA_HIP(hipGetDevice(&dev));
+    if (g_timer.device != dev || !g_timer.start) {
+        RPA_HIP(hipEventCreate(&g_timer.start));
+        RPA_HIP(hipEventCreate(&g_timer.stop));
+        g_timer.device = dev;
+    }
+    *a = g_timer.start;
+    *b = g_timer.stop;
+    return RPA_OK;
+}
+
+int tally(const Chi0Buf& b, int S, int64_t nd, SolveTally& t, hipStream_t s) {
     std::vector<int> it(S), st(S);
     RPA_HIP(hipMemcpyAsync(it.data(), b.iters, sizeof(int) * S, hipMemcpyDeviceToHost, s));
     RPA_HIP(hipMemcpyAsync(st.data(), b.status, sizeof(int) * S, hipMemcpyDeviceToHost, s));
     RPA_HIP(hipStreamSynchronize(s));
+    hipEvent_t e0, e1;
+    RPA_CHECK(timer_events(&e0, &e1));
+    float ms = 0.0f;
+    RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+    t.kernel_ms += ms;
+    t.launches += 1;
     for (int i = 0; i < S; ++i) {
+        t.point_iters += double(it[i]) * double(nd);
         t.iters_total += it[i];
         t.iters_max = std::max(t.iters_max, it[i]);
         t.unconv += (st[i] == 1);
@@ -284,6 +312,9 @@ void add_stats(rpa_stats* st, const SolveTally& t) {
     st->cocg_iters_max = std::max<int32_t>(st->cocg_iters_max, t.iters_max);
     st->n_unconverged += t.unconv;
     st->n_breakdown += t.breakdown;
+    st->cocg_launches += t.launches;
+    st->cocg_kernel_ms += t.kernel_ms;
+    st->cocg_point_iters += t.point_iters;
 }
 
 // Solve the Sternheimer systems of the trial vectors U[:, j0:j0+nv] at one frequency.
@@ -312,7 +343,11 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, double omega, const Opts& o
     L.iters = b.iters;
     L.status = b.status;
     L.fp32 = false;
+    hipEvent_t e0, e1;
+    RPA_CHECK(timer_events(&e0, &e1));
+    RPA_HIP(hipEventRecord(e0, s));
     RPA_HIP(launch_cocg(L, s));
+    RPA_HIP(hipEventRecord(e1, s));
     return RPA_OK;
 }
 
@@ -326,7 +361,7 @@ int chi0_apply(const rpa_cell* cell, const Grid& g, double omega, int nvec, cons
         RPA_CHECK(solve_chunk(cell, g, omega, o, b, in + nd * j0, nv, false, s));
         RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
                             out + nd * j0, s));
-        RPA_CHECK(tally(b, ns * nv, t, s));
+        RPA_CHECK(tally(b, ns * nv, nd, t, s));
     }
     return RPA_OK;
 }
@@ -668,7 +703,7 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
             RPA_CHECK(solve_chunk(cell, g, omega[m], o, b.xb, b.U + nd * j0, nv, true, s));
             RPA_HIP(launch_grad_accum_d(nd, ns, nv, cell->psi, b.xb.eps, omega[m], b.xb.coeff,
                                         b.xb.dbuf, b.coefk + j0, b.xb.x, false, grad_vloc, s));
-            RPA_CHECK(tally(b.xb, ns * nv, t, s));
+            RPA_CHECK(tally(b.xb, ns * nv, nd, t, s));
         }
         if (stats) stats->chi0_applies += 1;
     }

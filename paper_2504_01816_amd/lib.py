@@ -32,7 +32,9 @@ class RpaStats(ctypes.Structure):
     _fields_ = [("cocg_iters_total", c_int64), ("cocg_systems", c_int64),
                 ("cocg_iters_max", c_int32), ("n_unconverged", c_int32),
                 ("n_breakdown", c_int32), ("refinements", c_int32),
-                ("chi0_applies", c_int32), ("subspace_iters_total", c_int32)]
+                ("chi0_applies", c_int32), ("subspace_iters_total", c_int32),
+                ("cocg_launches", c_int64), ("cocg_kernel_ms", c_double),
+                ("cocg_point_iters", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(so):
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.RpaCell) == 48
     assert ctypes.sizeof(L.RpaOptions) == 48
-    assert ctypes.sizeof(L.RpaStats) == 40
+    assert ctypes.sizeof(L.RpaStats) == 64
 
 
 def _cell(n=(12, 12, 12), n_occ=4, h=0.5, eps=None):
