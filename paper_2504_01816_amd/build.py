@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librpa_gfx950.so")
-SOURCES = ["api.hip", "cocg.hip", "gemm.hip", "small.hip"]
+SOURCES = ["api.hip", "cocg.hip", "cocg_f64.hip", "cocg_mixed.hip", "gemm.hip", "small.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -27,26 +27,27 @@ def _run(cmd):
     return p
 
 
-def build(verbose=False):
-    objdir = os.path.join(HERE, "_build")
+def build(verbose=False, out=None, extra_flags=()):
+    objdir = os.path.join(HERE, "_build" if out is None else "_build_alt")
     os.makedirs(objdir, exist_ok=True)
     objs = []
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        _run([HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        _run([HIPCC, *FLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj])
         if verbose:
             print("compiled", src, flush=True)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    target = out or LIB
+    tmp = target + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
-    os.replace(tmp, LIB)
+    os.replace(tmp, target)
     if verbose:
-        print("built", LIB, flush=True)
-    return LIB
+        print("built", target, flush=True)
+    return target
 
 
 if __name__ == "__main__":

@@ -79,7 +79,6 @@ int read_opts(const rpa_options* o, Opts* out) {
     if (!(d.refine_tol > 0.0 && d.refine_tol < 1.0))
         return fail(RPA_EINVAL, "options.refine_tol must be in (0, 1)");
     if (d.max_systems < 0) return fail(RPA_EINVAL, "options.max_systems must be >= 0");
-    if (d.precision == RPA_MIXED) return fail(RPA_ENOTIMPL, "RPA_MIXED is not available yet");
     *out = d;
     return RPA_OK;
 }
@@ -141,11 +140,15 @@ void carve_coulomb(Carver& cv, const Grid& g, int nvec, CoulombBuf& b) {
 struct Chi0Buf {
     int chunk;     // trial vectors per COCG launch
     int nsplit;    // split-K of the coefficient GEMM
+    bool mixed;
+    bool x_complex;
     double* eps;
     double* coeff;
     double* part;
     void *r, *pa, *pb, *x;
-    int *iters, *status;
+    void* xlo;      // mixed only
+    double* b;      // mixed only
+    int *iters, *status, *refine;
     double2* dbuf;  // backward only
 };
 
@@ -168,17 +171,22 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     const int S = ns * b.chunk;
     const int64_t nd = g.nd();
     b.nsplit = coeff_split(nd, ns, S);
-    const size_t cplx = (o.precision == RPA_MIXED) ? 8 : 16;
-    const size_t real = cplx / 2;
+    b.mixed = (o.precision == RPA_MIXED);
+    // the mixed path keeps its solution as complex float64 (x_hi) for the true residual
+    b.x_complex = x_complex || b.mixed;
+    const size_t cplx = b.mixed ? 8 : 16;
     b.eps = cv.take<double>(ns);
     b.coeff = cv.take<double>(size_t(ns) * S);
     b.part = cv.take<double>(size_t(b.nsplit) * ns * S);
     b.r = cv.take<char>(size_t(S) * nd * cplx);
     b.pa = cv.take<char>(size_t(S) * nd * cplx);
     b.pb = cv.take<char>(size_t(S) * nd * cplx);
-    b.x = cv.take<char>(size_t(S) * nd * (x_complex ? cplx : real));
+    b.x = cv.take<char>(size_t(S) * nd * (b.x_complex ? 16 : 8));
+    b.xlo = b.mixed ? cv.take<char>(size_t(S) * nd * 8) : nullptr;
+    b.b = b.mixed ? cv.take<double>(size_t(S) * nd) : nullptr;
     b.iters = cv.take<int>(S);
     b.status = cv.take<int>(S);
+    b.refine = cv.take<int>(S);
     b.dbuf = with_d ? cv.take<double2>(size_t(ns) * S) : nullptr;
 }
 
@@ -258,7 +266,7 @@ int coulomb_apply(const Grid& g, const CoulombBuf& b, int power, int nvec, const
 }
 
 struct SolveTally {
-    int64_t iters_total = 0, systems = 0, launches = 0;
+    int64_t iters_total = 0, systems = 0, launches = 0, refinements = 0;
     int iters_max = 0, unconv = 0, breakdown = 0;
     double kernel_ms = 0.0, point_iters = 0.0;
 };
@@ -284,9 +292,11 @@ int timer_events(hipEvent_t* a, hipEvent_t* b) {
 }
 
 int tally(const Chi0Buf& b, int S, int64_t nd, SolveTally& t, hipStream_t s) {
-    std::vector<int> it(S), st(S);
+    std::vector<int> it(S), st(S), rf(S, 0);
     RPA_HIP(hipMemcpyAsync(it.data(), b.iters, sizeof(int) * S, hipMemcpyDeviceToHost, s));
     RPA_HIP(hipMemcpyAsync(st.data(), b.status, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+    if (b.mixed)
+        RPA_HIP(hipMemcpyAsync(rf.data(), b.refine, sizeof(int) * S, hipMemcpyDeviceToHost, s));
     RPA_HIP(hipStreamSynchronize(s));
     hipEvent_t e0, e1;
     RPA_CHECK(timer_events(&e0, &e1));
@@ -298,6 +308,7 @@ int tally(const Chi0Buf& b, int S, int64_t nd, SolveTally& t, hipStream_t s) {
         t.point_iters += double(it[i]) * double(nd);
         t.iters_total += it[i];
         t.iters_max = std::max(t.iters_max, it[i]);
+        t.refinements += rf[i];
         t.unconv += (st[i] == 1);
         t.breakdown += (st[i] == 2);
     }
@@ -312,6 +323,7 @@ void add_stats(rpa_stats* st, const SolveTally& t) {
     st->cocg_iters_max = std::max<int32_t>(st->cocg_iters_max, t.iters_max);
     st->n_unconverged += t.unconv;
     st->n_breakdown += t.breakdown;
+    st->refinements += int32_t(t.refinements);
     st->cocg_launches += t.launches;
     st->cocg_kernel_ms += t.kernel_ms;
     st->cocg_point_iters += t.point_iters;
@@ -324,8 +336,12 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, double omega, const Opts& o
     const int64_t nd = g.nd();
     const double dV = g.h * g.h * g.h;
     RPA_HIP(launch_proj_coeff(nd, ns, nv, dV, cell->psi, U, b.part, b.nsplit, b.coeff, s));
-    RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff,
-                                    reinterpret_cast<double*>(b.r), s));
+    if (b.mixed)
+        RPA_HIP(launch_proj_rhs<float>(nd, ns, nv, cell->psi, U, b.coeff,
+                                       reinterpret_cast<float*>(b.r), b.b, s));
+    else
+        RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff,
+                                        reinterpret_cast<double*>(b.r), nullptr, s));
     CocgLaunch L{};
     L.g = g;
     L.nsys = ns * nv;
@@ -342,7 +358,11 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, double omega, const Opts& o
     L.x_complex = x_complex;
     L.iters = b.iters;
     L.status = b.status;
-    L.fp32 = false;
+    L.fp32 = b.mixed;
+    L.xlo = b.xlo;
+    L.b = b.b;
+    L.refinements = b.refine;
+    L.refine_tol = o.refine_tol;
     hipEvent_t e0, e1;
     RPA_CHECK(timer_events(&e0, &e1));
     RPA_HIP(hipEventRecord(e0, s));
@@ -360,7 +380,7 @@ int chi0_apply(const rpa_cell* cell, const Grid& g, double omega, int nvec, cons
         const int nv = std::min(b.chunk, nvec - j0);
         RPA_CHECK(solve_chunk(cell, g, omega, o, b, in + nd * j0, nv, false, s));
         RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
-                            out + nd * j0, s));
+                            b.x_complex ? 2 : 1, out + nd * j0, s));
         RPA_CHECK(tally(b, ns * nv, nd, t, s));
     }
     return RPA_OK;
@@ -700,7 +720,7 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
         RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, b.W, b.U, s));
         for (int j0 = 0; j0 < nr; j0 += b.xb.chunk) {
             const int nv = std::min(b.xb.chunk, nr - j0);
-            RPA_CHECK(solve_chunk(cell, g, omega[m], o, b.xb, b.U + nd * j0, nv, true, s));
+            RPA_CHECK(solve_chunk(cell, g, omega[m], o, b.xb, b.U + nd * j0, nv, b.xb.x_complex, s));
             RPA_HIP(launch_grad_accum_d(nd, ns, nv, cell->psi, b.xb.eps, omega[m], b.xb.coeff,
                                         b.xb.dbuf, b.coefk + j0, b.xb.x, false, grad_vloc, s));
             RPA_CHECK(tally(b.xb, ns * nv, nd, t, s));

@@ -1,0 +1,606 @@
+// Batched COCG kernel for the shifted Sternheimer systems (H - eps_n - i omega) x = b
+// (Sec. 3: COCG, conjugate gradients with the unconjugated bilinear form; Eq. 9).
+//
+// Design (gfx950):
+//  * One workgroup owns one system for its whole solve.  The reductions of a COCG
+//    iteration are workgroup-local, so a system runs all its iterations inside one launch
+//    with no host round trip.  Systems converge independently; a finished workgroup frees
+//    its CU slot and the dispatcher starts the next system (active-set compaction).
+//  * An iteration is two streaming sweeps over the system:
+//      sweep 1: p <- r + beta p (into the other p buffer), q = A p; reduce p^T q, |p|^2, |q|^2
+//      sweep 2: q = A p again (q is never stored), x <- x + alpha p, r <- r - alpha q;
+//               reduce r^T r, |r|^2.
+//  * A sweep marches along z, Z planes per step.  Thread t owns columns t, t+BS, ... of
+//    the x-y plane and holds planes z-6 .. z+5+Z of the swept vector in a register queue;
+//    the Z current planes are staged in LDS (double buffered) for the x and y neighbours.
+//    The next step's planes are loaded before the current step computes, and the barrier
+//    only orders LDS (global loads and stores stay in flight): every global address is
+//    read and written by one thread only, so LDS is the sole cross-thread channel.
+//  * Mixed precision (T = float): r, p and the partial solution x_lo are complex64; the
+//    solution x_hi and the right-hand side b are float64.  When the complex64 residual has
+//    dropped by refine_tol since the last refinement (or reaches the tolerance), the
+//    partial solution is folded into x_hi and r is replaced by the true residual b - A x_hi
+//    computed in float64 (reliable update); p and the Krylov recurrence continue.  The
+//    tolerance test uses that float64 residual.
+//  * Reductions accumulate in float64 and are fixed-order: results are bitwise
+//    reproducible run to run.
+// Layout: state arrays are system-major, nsys x N_d, complex interleaved (re, im).
+// Constraints: n2 >= 12 and divisible by Z; n0, n1 >= 7.
+#pragma once
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace rpa {
+namespace cocg {
+
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
+struct Args {
+    int n0, n1, n2, P;
+    double cw[7];          // cw[k] = -1/2 w_k / h^2 for k >= 1; cw[0] = -1/2 * 3 w_0 / h^2
+    const double* vloc;
+    const double* eps;
+    int ns;
+    double omega;
+    double tol2;
+    double refine2;        // mixed: refine_tol^2
+    int max_iter;
+    double bd_tol;
+    int64_t nd;
+    void* r;               // complex T
+    void* pa;              // complex T
+    void* pb;              // complex T
+    void* x;               // FP64 path: real or complex double; mixed: complex double x_hi
+    void* xlo;             // mixed: complex float
+    const double* b;       // mixed: real double right-hand side
+    int* iters;
+    int* status;
+    int* refinements;      // mixed: per system
+    int nbuf;              // LDS plane buffers (2: one barrier per step, 1: two barriers)
+};
+
+// Element access through a uniform base pointer and a 32-bit unsigned offset, so loads and
+// stores use the SGPR-base + 32-bit VGPR-offset addressing form (system size < 2^26 points).
+template <typename V>
+__device__ __forceinline__ V ld(const V* base, unsigned idx) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * unsigned(sizeof(V)));
+}
+template <typename V>
+__device__ __forceinline__ void st(V* base, unsigned idx, V v) {
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * unsigned(sizeof(V))) = v;
+}
+
+#ifndef RPA_PREFETCH
+#define RPA_PREFETCH 1
+#endif
+
+// Compiler fence between groups of stencil LDS reads (bounds the reads in flight).
+#ifndef RPA_LDS_GROUP_FENCE
+#define RPA_LDS_GROUP_FENCE() asm volatile("" ::: "memory")
+#endif
+
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int NV>
+__device__ __forceinline__ void wg_reduce(double (&v)[NV], double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * NV + k];
+        v[k] = s;
+    }
+    lds_barrier();
+}
+
+template <int C>
+struct Cols {
+    int col[C], cx[C], cy[C];
+    bool valid[C];
+};
+
+// LDS plane layout: rows of RS = n0 + 12 entries; row y holds x = -6 .. n0+5 (periodic
+// ghosts on both sides), so x neighbours are fixed offsets from a point; y neighbours are
+// addressed with the periodic wrap of the row index.
+__device__ __forceinline__ int lds_center(int n0, int cx, int cy) { return cy * (n0 + 12) + cx + 6; }
+
+template <typename Q2>
+__device__ __forceinline__ void stage_point(Q2* L, int n0, int cx, int cy, Q2 v) {
+    const int c0 = lds_center(n0, cx, cy);
+    L[c0] = v;
+    if (cx < 6) L[c0 + n0] = v;
+    if (cx >= n0 - 6) L[c0 - n0] = v;
+}
+
+// q = (A c) for one column: A = -1/2 Lap_h + V - eps - i omega; x/y neighbours from the
+// LDS plane L, z neighbours from the queue entries Q[zc-6 .. zc+6][i].
+template <typename R, typename Q2, int NQ, int C>
+__device__ __forceinline__ Q2 stencil(const Args& a, const Q2* __restrict__ L, const Q2 (&Q)[NQ][C],
+                                      int zc, int i, int cx, int cy, R diag, R om) {
+    const int n0 = a.n0, n1 = a.n1, RS = n0 + 12;
+    // keep the row index opaque so that neighbour addresses are formed here, not hoisted
+    // out of the z loop into long-lived registers
+    asm volatile("" : "+v"(cy));
+    const Q2* Lc = L + cy * RS + cx + 6;
+    R ax = 0, ay = 0;
+    // neighbours are read in groups of four LDS loads; the fence keeps the compiler from
+    // issuing all 24 reads (and their registers) ahead of use
+#pragma unroll
+    for (int k = 1; k <= 6; k += 2) {
+        const Q2 a1 = Lc[k], a2 = Lc[-k], a3 = Lc[k + 1], a4 = Lc[-k - 1];
+        ax += R(a.cw[k]) * (a1.x + a2.x) + R(a.cw[k + 1]) * (a3.x + a4.x);
+        ay += R(a.cw[k]) * (a1.y + a2.y) + R(a.cw[k + 1]) * (a3.y + a4.y);
+        RPA_LDS_GROUP_FENCE();
+    }
+#pragma unroll
+    for (int k = 1; k <= 6; k += 2) {
+        int yp = cy + k; yp -= (yp >= n1) ? n1 : 0;
+        int ym = cy - k; ym += (ym < 0) ? n1 : 0;
+        int yp2 = cy + k + 1; yp2 -= (yp2 >= n1) ? n1 : 0;
+        int ym2 = cy - k - 1; ym2 += (ym2 < 0) ? n1 : 0;
+        const Q2 b1 = L[yp * RS + cx + 6], b2 = L[ym * RS + cx + 6];
+        const Q2 b3 = L[yp2 * RS + cx + 6], b4 = L[ym2 * RS + cx + 6];
+        ax += R(a.cw[k]) * (b1.x + b2.x) + R(a.cw[k + 1]) * (b3.x + b4.x);
+        ay += R(a.cw[k]) * (b1.y + b2.y) + R(a.cw[k + 1]) * (b3.y + b4.y);
+        RPA_LDS_GROUP_FENCE();
+    }
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) {
+        const Q2 c1 = Q[zc + k][i], c2 = Q[zc - k][i];
+        ax += R(a.cw[k]) * (c1.x + c2.x);
+        ay += R(a.cw[k]) * (c1.y + c2.y);
+    }
+    const Q2 c = Q[zc][i];
+    return Q2{ax + diag * c.x + om * c.y, ay + diag * c.y - om * c.x};
+}
+
+// Generic z-march: lead.load(z, i) fetches what the queue entry of plane z needs,
+// lead.make(buf) turns it into the queue value; cent.load(z, i) fetches what the centre
+// step needs, cent.finish(buf, z, i, c, q) consumes the stencil result.  Loads for step
+// s+1 are issued before step s computes.
+// Q is the caller's queue.  With warm = true it already holds planes -6 .. 5 (mod n2) of the
+// lead vector in Q[0..11] and the warm-up is skipped.  On return Q[0..11] holds planes
+// -6 .. 5 of the lead vector again (the queue has wrapped around the periodic z axis).
+template <typename R, typename Q2, int C, int Z, class Lead, class Cent>
+__device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds, double eps_n,
+                                      Lead& lead, Cent& cent, Q2 (&Q)[12 + Z][C], bool warm) {
+    constexpr int NQ = 12 + Z;
+    const int n2 = a.n2, P = a.P;
+    const R om = R(a.omega);
+    typename Lead::Buf LB[Z][C];
+    typename Cent::Buf CB[Z][C];
+    // warm-up: push planes -6 .. 5 through the top of the queue, Z at a time
+#pragma unroll 1
+    for (int w = 0; w < (warm ? 0 : 12 / Z); ++w) {
+#pragma unroll
+        for (int zz = 0; zz < Z; ++zz) {
+            int z = w * Z + zz - 6;
+            z += (z < 0) ? n2 : 0;
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                Q[12 + zz][i] = cl.valid[i] ? lead.make(lead.load(z, i)) : Q2{0, 0};
+        }
+#pragma unroll
+        for (int s = 0; s < 12; ++s)
+#pragma unroll
+            for (int i = 0; i < C; ++i) Q[s][i] = Q[s + Z][i];
+    }
+#pragma unroll
+    for (int zz = 0; zz < Z; ++zz) {
+        int z = 6 + zz;
+        z -= (z >= n2) ? n2 : 0;
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            if (cl.valid[i]) {
+                LB[zz][i] = lead.load(z, i);
+                CB[zz][i] = cent.load(zz, i);
+            }
+        }
+    }
+    const int nsteps = n2 / Z;
+#pragma unroll 1
+    for (int st = 0; st < nsteps; ++st) {
+        const int zo = st * Z;
+        typename Cent::Buf CC[Z][C];
+        if (!RPA_PREFETCH && st > 0) {
+#pragma unroll
+            for (int zz = 0; zz < Z; ++zz) {
+                int z = zo + 6 + zz;
+                z -= (z >= n2) ? n2 : 0;
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    if (cl.valid[i]) {
+                        LB[zz][i] = lead.load(z, i);
+                        CB[zz][i] = cent.load(zo + zz, i);
+                    }
+            }
+        }
+#pragma unroll
+        for (int zz = 0; zz < Z; ++zz)
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                Q[12 + zz][i] = cl.valid[i] ? lead.make(LB[zz][i]) : Q2{0, 0};
+                CC[zz][i] = CB[zz][i];
+            }
+        if (RPA_PREFETCH && st + 1 < nsteps) {
+#pragma unroll
+            for (int zz = 0; zz < Z; ++zz) {
+                int z = zo + Z + 6 + zz;
+                z -= (z >= n2) ? n2 : 0;
+                z -= (z >= n2) ? n2 : 0;
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    if (cl.valid[i]) {
+                        LB[zz][i] = lead.load(z, i);
+                        CB[zz][i] = cent.load(zo + Z + zz, i);
+                    }
+                }
+            }
+        }
+        const int PL = a.n1 * (a.n0 + 12);       // padded plane
+        Q2* L = lds + (a.nbuf == 2 ? (st & 1) : 0) * Z * PL;
+#pragma unroll
+        for (int zz = 0; zz < Z; ++zz)
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                if (cl.valid[i]) stage_point(L + zz * PL, a.n0, cl.cx[i], cl.cy[i], Q[6 + zz][i]);
+        lds_barrier();
+#pragma unroll
+        for (int zz = 0; zz < Z; ++zz) {
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                if (!cl.valid[i]) continue;
+                const unsigned idx = unsigned((zo + zz) * P + cl.col[i]);
+                const R diag = R(a.cw[0] + ld(a.vloc, idx) - eps_n);
+                const Q2 q = stencil<R, Q2, NQ, C>(a, L + zz * PL, Q, 6 + zz, i, cl.cx[i], cl.cy[i],
+                                                   diag, om);
+                cent.finish(CC[zz][i], zo + zz, i, Q[6 + zz][i], q);
+            }
+        }
+        if (a.nbuf == 1) lds_barrier();      // single buffer: reads done before the next write
+#pragma unroll
+        for (int s = 0; s < 12; ++s)
+#pragma unroll
+            for (int i = 0; i < C; ++i) Q[s][i] = Q[s + Z][i];
+    }
+}
+
+struct Empty {};
+
+// ---------------------------------------------------------------- sweep 1 (sigma)
+template <typename T2, int C>
+struct LeadPnew {
+    struct Buf { T2 r, p; };
+    const T2* r; const T2* pa; int P; const int* col; bool first; double dbr, dbi;
+    __device__ Buf load(int z, int i) const {
+        const unsigned idx = unsigned(z * P + col[i]);
+        Buf b;
+        b.r = ld(r, idx);
+        b.p = first ? T2{0, 0} : ld(pa, idx);
+        return b;
+    }
+    __device__ T2 make(const Buf& b) const {
+        using R = decltype(T2{}.x);
+        const R br_ = R(dbr), bi_ = R(dbi);
+        return T2{b.r.x + br_ * b.p.x - bi_ * b.p.y, b.r.y + br_ * b.p.y + bi_ * b.p.x};
+    }
+};
+template <typename T2, int C>
+struct CentSigma {
+    using Buf = Empty;
+    T2* pb; int P; const int* col; bool first;
+    double acc[7];   // sigma re/im, |p|^2, |q|^2, rho0 re/im, |r0|^2
+    __device__ Buf load(int, int) const { return Buf{}; }
+    __device__ void finish(const Buf&, int z, int i, T2 c, T2 q) {
+        acc[0] += double(c.x) * q.x - double(c.y) * q.y;
+        acc[1] += double(c.x) * q.y + double(c.y) * q.x;
+        acc[2] += double(c.x) * c.x + double(c.y) * c.y;
+        acc[3] += double(q.x) * q.x + double(q.y) * q.y;
+        if (first) {
+            acc[4] += double(c.x) * c.x - double(c.y) * c.y;
+            acc[5] += 2.0 * double(c.x) * c.y;
+            acc[6] += double(c.x) * c.x + double(c.y) * c.y;
+        }
+        st(pb, unsigned(z * P + col[i]), c);
+    }
+};
+
+// ---------------------------------------------------------------- sweep 2 (update)
+template <typename T2>
+struct LeadLoad {
+    using Buf = T2;
+    const T2* v; int P; const int* col;
+    __device__ Buf load(int z, int i) const { return ld(v, unsigned(z * P + col[i])); }
+    __device__ T2 make(const Buf& b) const { return b; }
+};
+// x stored as XS (double: real part only, double2: complex FP64, float2: complex64 x_lo)
+template <typename T2, typename XS>
+struct CentUpdate {
+    struct Buf { T2 r; XS x; };
+    T2* r; XS* x; int P; const int* col; bool xzero; double ar, ai;
+    double acc[3];   // rho' re/im, |r|^2
+    __device__ Buf load(int z, int i) const {
+        const unsigned idx = unsigned(z * P + col[i]);
+        Buf b;
+        b.r = ld(r, idx);
+        if (xzero) b.x = XS{}; else b.x = ld(x, idx);
+        return b;
+    }
+    __device__ void finish(const Buf& bf, int z, int i, T2 c, T2 q) {
+        using R = decltype(T2{}.x);
+        const unsigned idx = unsigned(z * P + col[i]);
+        const R a_r = R(ar), a_i = R(ai);
+        T2 rv = bf.r;
+        rv.x -= a_r * q.x - a_i * q.y;
+        rv.y -= a_r * q.y + a_i * q.x;
+        st(r, idx, rv);
+        XS xv = bf.x;
+        if constexpr (std::is_same<XS, double>::value) {
+            xv += double(a_r) * c.x - double(a_i) * c.y;
+        } else {
+            xv.x += a_r * c.x - a_i * c.y;
+            xv.y += a_r * c.y + a_i * c.x;
+        }
+        st(x, idx, xv);
+        acc[0] += double(rv.x) * rv.x - double(rv.y) * rv.y;
+        acc[1] += 2.0 * double(rv.x) * rv.y;
+        acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+    }
+};
+
+// ---------------------------------------------------------------- reliable update (mixed)
+// pointwise x_hi <- x_hi + x_lo (FP64) over the thread's own columns, so that every global
+// address keeps a single reader and writer
+template <int C>
+__device__ __forceinline__ void fold_xlo(const Args& a, const int (&col)[C], const bool (&valid)[C],
+                                         double2* xhi, const float2* xlo, bool xhi_zero) {
+    for (int z = 0; z < a.n2; ++z) {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            if (!valid[i]) continue;
+            const unsigned idx = unsigned(z * a.P + col[i]);
+            const float2 l = ld(xlo, idx);
+            double2 h = xhi_zero ? double2{0.0, 0.0} : ld(xhi, idx);
+            h.x += double(l.x);
+            h.y += double(l.y);
+            st(xhi, idx, h);
+        }
+    }
+}
+// True residual r = b - A x_hi in float64, stored as complex64 (reliable update).  This
+// sweep runs once per refinement, so it keeps no register queue: the z neighbours of x_hi
+// are read straight from global memory (each thread reads only its own columns), the x
+// and y neighbours come from the LDS plane.  Returns rho = r^T r and |r|^2 in acc.
+template <int C>
+__device__ __forceinline__ void true_residual(const Args& a, const Cols<C>& cl, double2* lds,
+                                              double eps_n, const double2* xhi, const double* b,
+                                              float2* r, double (&acc)[3]) {
+    const int n2 = a.n2, P = a.P, n0 = a.n0, n1 = a.n1, RS = n0 + 12;
+    acc[0] = acc[1] = acc[2] = 0.0;
+    for (int z = 0; z < n2; ++z) {
+        double2* L = lds;
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            if (cl.valid[i])
+                stage_point(L, n0, cl.cx[i], cl.cy[i], ld(xhi, unsigned(z * P + cl.col[i])));
+        lds_barrier();
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            if (!cl.valid[i]) continue;
+            const int cx = cl.cx[i], cy = cl.cy[i];
+            const double2* Lc = L + lds_center(n0, cx, cy);
+            const double2 c = Lc[0];
+            double ax = 0, ay = 0;
+#pragma unroll
+            for (int k = 1; k <= 6; ++k) {
+                int yp = cy + k; yp -= (yp >= n1) ? n1 : 0;
+                int ym = cy - k; ym += (ym < 0) ? n1 : 0;
+                int zp = z + k; zp -= (zp >= n2) ? n2 : 0;
+                int zm = z - k; zm += (zm < 0) ? n2 : 0;
+                const double2 a1 = Lc[k], a2 = Lc[-k];
+                const double2 b1 = L[yp * RS + cx + 6], b2 = L[ym * RS + cx + 6];
+                const double2 c1 = ld(xhi, unsigned(zp * P + cl.col[i]));
+                const double2 c2 = ld(xhi, unsigned(zm * P + cl.col[i]));
+                ax += a.cw[k] * ((a1.x + a2.x) + (b1.x + b2.x) + (c1.x + c2.x));
+                ay += a.cw[k] * ((a1.y + a2.y) + (b1.y + b2.y) + (c1.y + c2.y));
+            }
+            const unsigned idx = unsigned(z * P + cl.col[i]);
+            const double diag = a.cw[0] + ld(a.vloc, idx) - eps_n;
+            const double qx = ax + diag * c.x + a.omega * c.y;
+            const double qy = ay + diag * c.y - a.omega * c.x;
+            const float2 rv = float2{float(ld(b, idx) - qx), float(-qy)};
+            st(r, idx, rv);
+            acc[0] += double(rv.x) * rv.x - double(rv.y) * rv.y;
+            acc[1] += 2.0 * double(rv.x) * rv.y;
+            acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+        }
+        lds_barrier();                    // one buffer: all reads done before the next plane
+    }
+}
+
+// ---------------------------------------------------------------- the solver
+// T: state precision (double: FP64 path, float: mixed); XS: type of the stored solution in
+// the FP64 path (double = real part only, double2 = complex); ignored when T = float.
+template <typename T, typename XS, int C, int Z, int BSMAX>
+__global__ __launch_bounds__(BSMAX) void cocg_wg(Args a) {
+    using T2 = typename Cplx<T>::type;
+    constexpr bool MIXED = std::is_same<T, float>::value;
+    const int sys = blockIdx.x;
+    const int tid = threadIdx.x, BS = blockDim.x;
+    const int n0 = a.n0, P = a.P;
+    const int64_t off = int64_t(sys) * a.nd;
+    T2* r = reinterpret_cast<T2*>(a.r) + off;
+    T2* pa = reinterpret_cast<T2*>(a.pa) + off;
+    T2* pb = reinterpret_cast<T2*>(a.pb) + off;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* red = reinterpret_cast<double*>(smem_raw);                // 16 waves x 8
+    unsigned char* planes = smem_raw + 16 * 8 * sizeof(double);
+    const double eps_n = a.eps[sys % a.ns];
+
+    Cols<C> cl;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        cl.col[i] = tid + i * BS;
+        cl.valid[i] = cl.col[i] < P;
+        const int cc = cl.valid[i] ? cl.col[i] : 0;
+        cl.cx[i] = cc % n0;
+        cl.cy[i] = cc / n0;
+    }
+
+    double rho_re = 0, rho_im = 0, bb = 0, beta_re = 0, beta_im = 0, rr_ref = 0;
+    int it = 0, st = 0, nref = 0;
+    bool xlo_zero = true, xhi_zero = true, done = false;
+    // Queue of the swept vector, carried from sweep to sweep: after sweep 1 it holds planes
+    // -6 .. 5 of the new p, which is what sweep 2 starts from; after sweep 2 it still holds
+    // those planes of p, and the next sweep 1 starts from r' + beta' p on them.
+    T2 Q[12 + Z][C];
+
+    while (!done) {
+        const bool first = (it == 0);
+        // ---------------------------------------------------------- sweep 1
+        if (!first) {
+            // warm start of sweep 1 from the queue: p_new = r + beta p on planes -6 .. 5
+            T2 rw[12][C];
+#pragma unroll
+            for (int s = 0; s < 12; ++s) {
+                int z = s - 6;
+                z += (z < 0) ? a.n2 : 0;
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    rw[s][i] = cl.valid[i] ? ld(r, unsigned(z * P + cl.col[i])) : T2{0, 0};
+            }
+            const T br = T(beta_re), bi = T(beta_im);
+#pragma unroll
+            for (int s = 0; s < 12; ++s)
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const T2 pv = Q[s][i];
+                    Q[s][i] = T2{rw[s][i].x + br * pv.x - bi * pv.y,
+                                 rw[s][i].y + br * pv.y + bi * pv.x};
+                }
+        }
+        LeadPnew<T2, C> l1{r, pa, P, cl.col, first, beta_re, beta_im};
+        CentSigma<T2, C> c1{pb, P, cl.col, first, {0, 0, 0, 0, 0, 0, 0}};
+        march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q, !first);
+        wg_reduce<7>(c1.acc, red);
+        if (first) {
+            rho_re = c1.acc[4];
+            rho_im = c1.acc[5];
+            bb = c1.acc[6];
+            rr_ref = bb;
+        }
+        const bool zero_rhs = first && !(bb > 0.0);
+        bool breakdown = false;
+        double alpha_re = 0, alpha_im = 0;
+        if (!zero_rhs) {
+            ++it;
+            const double s2 = c1.acc[0] * c1.acc[0] + c1.acc[1] * c1.acc[1];
+            if (!(s2 > a.bd_tol * a.bd_tol * c1.acc[2] * c1.acc[3])) {
+                breakdown = true;
+            } else {
+                alpha_re = (rho_re * c1.acc[0] + rho_im * c1.acc[1]) / s2;
+                alpha_im = (rho_im * c1.acc[0] - rho_re * c1.acc[1]) / s2;
+            }
+        }
+        // ---------------------------------------------------------- sweep 2
+        double acc2[3];
+        {
+            LeadLoad<T2> l2{pb, P, cl.col};
+            if constexpr (MIXED) {
+                CentUpdate<T2, float2> c2{r, reinterpret_cast<float2*>(a.xlo) + off, P, cl.col,
+                                          xlo_zero, alpha_re, alpha_im, {0, 0, 0}};
+                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q, true);
+                wg_reduce<3>(c2.acc, red);
+                acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
+            } else {
+                CentUpdate<T2, XS> c2{r, reinterpret_cast<XS*>(a.x) + off, P, cl.col, first,
+                                      alpha_re, alpha_im, {0, 0, 0}};
+                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q, true);
+                wg_reduce<3>(c2.acc, red);
+                acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
+            }
+        }
+        xlo_zero = false;
+        if (zero_rhs) {
+            done = true;
+        } else if (breakdown) {
+            st = 2;
+            done = true;
+        } else {
+            bool conv = false;
+            if constexpr (MIXED) {
+                // reliable update when the complex64 residual fell by refine_tol or hit tol
+                if (acc2[2] <= a.tol2 * bb || acc2[2] <= a.refine2 * rr_ref) {
+                    fold_xlo<C>(a, cl.col, cl.valid, reinterpret_cast<double2*>(a.x) + off,
+                                reinterpret_cast<const float2*>(a.xlo) + off, xhi_zero);
+                    xhi_zero = false;
+                    xlo_zero = true;
+                    ++nref;
+                    double acc3[3];
+                    true_residual<C>(a, cl, reinterpret_cast<double2*>(planes), eps_n,
+                                     reinterpret_cast<const double2*>(a.x) + off, a.b + off,
+                                     reinterpret_cast<float2*>(r), acc3);
+                    wg_reduce<3>(acc3, red);
+                    acc2[0] = acc3[0]; acc2[1] = acc3[1]; acc2[2] = acc3[2];
+                    rr_ref = acc2[2];
+                    conv = acc2[2] <= a.tol2 * bb;
+                }
+            } else {
+                conv = acc2[2] <= a.tol2 * bb;
+            }
+            if (conv) {
+                done = true;
+            } else if (it >= a.max_iter) {
+                st = 1;
+                done = true;
+            } else {
+                const double n2r = acc2[0] * acc2[0] + acc2[1] * acc2[1];
+                if (!(n2r > a.bd_tol * a.bd_tol * acc2[2] * acc2[2])) {
+                    st = 2;
+                    done = true;
+                } else {
+                    const double rr = rho_re * rho_re + rho_im * rho_im;
+                    beta_re = (acc2[0] * rho_re + acc2[1] * rho_im) / rr;
+                    beta_im = (acc2[1] * rho_re - acc2[0] * rho_im) / rr;
+                    rho_re = acc2[0];
+                    rho_im = acc2[1];
+                    T2* t = pa;
+                    pa = pb;
+                    pb = t;
+                }
+            }
+        }
+    }
+    if constexpr (MIXED) {
+        // the solution lives in x_hi: fold the last partial solution if it is pending
+        if (!xlo_zero)
+            fold_xlo<C>(a, cl.col, cl.valid, reinterpret_cast<double2*>(a.x) + off,
+                        reinterpret_cast<const float2*>(a.xlo) + off, xhi_zero);
+    }
+    if (tid == 0) {
+        a.iters[sys] = it;
+        a.status[sys] = st;
+        if (a.refinements) a.refinements[sys] = nref;
+    }
+}
+
+}  // namespace cocg
+}  // namespace rpa

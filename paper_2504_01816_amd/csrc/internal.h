@@ -76,10 +76,11 @@ hipError_t launch_proj_coeff(int64_t nd, int ns, int nvec, double dV, const doub
                              const double* U, double* part, int nsplit, double* coeff,
                              hipStream_t s);
 // r0[s][r] = -(psi[r,n] u[r,j] - sum_l psi[r,l] coeff[l,s]) written as complex (T = float or
-// double) with zero imaginary part.
+// double) with zero imaginary part; if b64 != null the same value is also written there as a
+// real float64 right-hand side.
 template <typename T>
 hipError_t launch_proj_rhs(int64_t nd, int ns, int nvec, const double* psi, const double* U,
-                           const double* coeff, T* r0, hipStream_t s);
+                           const double* coeff, T* r0, double* b64, hipStream_t s);
 
 // Batched COCG, one workgroup per system.  See cocg.hip for the layout.
 struct CocgLaunch {
@@ -94,17 +95,22 @@ struct CocgLaunch {
     void* r;               // nsys x N_d complex (T2)
     void* pa;              // nsys x N_d complex
     void* pb;              // nsys x N_d complex
-    void* x;               // nsys x N_d real (or complex if x_complex)
+    void* x;               // FP64: nsys x N_d real (complex if x_complex); mixed: complex FP64
     bool x_complex;
     int* iters;            // nsys
     int* status;           // nsys (0 ok, 1 not converged, 2 breakdown)
-    bool fp32;             // state in complex64
+    bool fp32;             // mixed precision: state in complex64, reliable updates in FP64
+    void* xlo;             // mixed: nsys x N_d complex64 partial solution
+    const double* b;       // mixed: nsys x N_d real right-hand side
+    int* refinements;      // mixed: nsys (may be null)
+    double refine_tol;     // mixed: residual drop that triggers a reliable update
 };
 hipError_t launch_cocg(const CocgLaunch& a, hipStream_t s);
 
-// Delta rho epilogue: out[r, j] = 4 sum_n psi[r,n] xre[n + ns*j][r]
-hipError_t launch_drho(int64_t nd, int ns, int nvec, const double* psi, const double* xre,
-                       double* out, hipStream_t s);
+// Delta rho epilogue: out[r, j] = 4 sum_n psi[r,n] Re x[n + ns*j][r]; x is float64 with
+// `stride` doubles per point (1: real parts only, 2: complex interleaved)
+hipError_t launch_drho(int64_t nd, int ns, int nvec, const double* psi, const double* x,
+                       int stride, double* out, hipStream_t s);
 
 // Dense FP64 helpers on small N_r x N_r matrices and tall N_d x N_r blocks.
 // G = A^T B (A: nd x m, B: nd x m, both column-major), G: m x m column-major; split-K.
@@ -134,8 +140,6 @@ hipError_t launch_grad_accum_d(int64_t nd, int ns, int nvec, const double* psi,
                                const double* eps, double omega, const double* coeff,
                                double2* dbuf, const double* coefk, const void* x, bool x_fp32,
                                double* grad, hipStream_t s);
-hipError_t launch_drho_f32(int64_t nd, int ns, int nvec, const double* psi, const float* xre,
-                           double* out, hipStream_t s);
 hipError_t launch_scale(int64_t n, double a, double* x, hipStream_t s);
 hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t s);
 hipError_t launch_fill(int64_t n, double v, double* x, hipStream_t s);

@@ -201,14 +201,14 @@ __global__ __launch_bounds__(SB) void syevj_kernel(int m, const double* Ain, dou
     }
 }
 
-template <typename X>
-__global__ void drho_kernel(int64_t nd, int ns, const double* psi, const X* xre, double* out) {
+template <int STRIDE>
+__global__ void drho_kernel(int64_t nd, int ns, const double* psi, const double* x, double* out) {
     const int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int j = blockIdx.y;
     if (r >= nd) return;
     double s = 0.0;
     for (int n = 0; n < ns; ++n)
-        s += psi[r + nd * n] * double(xre[(int64_t(n) + int64_t(ns) * j) * nd + r]);
+        s += psi[r + nd * n] * x[STRIDE * ((int64_t(n) + int64_t(ns) * j) * nd + r)];
     out[r + nd * j] = 4.0 * s;
 }
 
@@ -298,17 +298,13 @@ hipError_t launch_syevj(int m, const double* A, double* work, double* w, double*
     return hipGetLastError();
 }
 
-hipError_t launch_drho(int64_t nd, int ns, int nvec, const double* psi, const double* xre,
-                       double* out, hipStream_t s) {
-    hipLaunchKernelGGL(drho_kernel<double>, dim3(unsigned((nd + 255) / 256), nvec), dim3(256), 0,
-                       s, nd, ns, psi, xre, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_drho_f32(int64_t nd, int ns, int nvec, const double* psi, const float* xre,
-                           double* out, hipStream_t s) {
-    hipLaunchKernelGGL(drho_kernel<float>, dim3(unsigned((nd + 255) / 256), nvec), dim3(256), 0,
-                       s, nd, ns, psi, xre, out);
+hipError_t launch_drho(int64_t nd, int ns, int nvec, const double* psi, const double* x,
+                       int stride, double* out, hipStream_t s) {
+    const dim3 grid(unsigned((nd + 255) / 256), nvec);
+    if (stride == 2)
+        hipLaunchKernelGGL(drho_kernel<2>, grid, dim3(256), 0, s, nd, ns, psi, x, out);
+    else
+        hipLaunchKernelGGL(drho_kernel<1>, grid, dim3(256), 0, s, nd, ns, psi, x, out);
     return hipGetLastError();
 }
 

@@ -8,7 +8,7 @@ import os
 from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librpa_gfx950.so")
+LIB_PATH = os.environ.get("RPA_LIB_PATH") or os.path.join(HERE, "librpa_gfx950.so")
 
 RPA_OK, RPA_ENOTCONV = 0, 1
 RPA_EINVAL, RPA_EWORKSPACE, RPA_EBREAKDOWN, RPA_ENOTPD, RPA_EHIP, RPA_ENOTIMPL = -1, -2, -3, -4, -5, -6

@@ -172,3 +172,55 @@ def test_backward_matches_oracle_adjoint():
     Cs = [res["Csave"][0][m].cpu().numpy() for m in range(2)]
     ref = ograd.energy_backward(c.vloc, c.psi.T, c.eps, c.shape, c.h, om, W, Vs, Cs, 1e-12, 5000)
     assert rel(grad.cpu().numpy(), ref) < 1e-8
+
+
+# ---------------------------------------------------------------------------- mixed precision
+MIXED = 1
+
+
+def test_mixed_chi0_matches_oracle(wl0, dc0):
+    c = wl0.cells[0]
+    say("mixed chi0 12^3 16 vectors tol 1e-10")
+    U = np.random.default_rng(2).standard_normal((16, c.nd))
+    out, rc, st = api.rpa_apply_chi0(dc0, 1.0, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-10, precision=MIXED))
+    ref, iters, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, 1.0, c.shape, c.h, 1e-10, 5000)
+    assert rc == 0 and st["n_unconverged"] == 0 and st["refinements"] >= 64
+    assert rel(out.cpu().numpy().T, ref) < 1e-9
+
+
+@pytest.mark.parametrize("omega", [0.02, 8.8])
+def test_mixed_chi0_extreme_frequencies(wl0, dc0, omega):
+    c = wl0.cells[0]
+    say("mixed chi0 omega", omega)
+    U = np.random.default_rng(3).standard_normal((4, c.nd))
+    out, rc, st = api.rpa_apply_chi0(dc0, omega, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-10, precision=MIXED))
+    ref, _, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, omega, c.shape, c.h, 1e-10, 5000)
+    assert rc == 0 and rel(out.cpu().numpy().T, ref) < 1e-9
+
+
+def test_mixed_energy_matches_oracle(wl0, dc0, oracle_e0):
+    say("mixed rpa_energy 12^3")
+    V0 = torch.tensor(wl0.V0[0], device=DEV)
+    res = api.rpa_energy(dc0, 16, wl0.omegas, wl0.weights, [V0],
+                         dict(cocg_tol=1e-10, subspace_iters=5, ec_tol=0.0, precision=MIXED))
+    E = res["E_c"][0]
+    say("E_c mixed %.15e oracle %.15e" % (E, oracle_e0["E_c"]))
+    assert res["status"] == 0
+    assert abs(E - oracle_e0["E_c"]) <= 1e-9 * abs(oracle_e0["E_c"])
+
+
+def test_mixed_backward_matches_fp64():
+    say("mixed backward vs fp64 backward 12^3")
+    c = synth.small_cell(n=12, h=0.5, n_wells=2, n_occ=3, seed=11)
+    dc = api.device_cell(c, DEV)
+    om, W = np.array([2.0, 0.7]), np.array([0.6, 0.9])
+    V0 = np.random.default_rng(6).standard_normal((6, c.nd))
+    o64 = dict(cocg_tol=1e-11, subspace_iters=3, ec_tol=0.0)
+    res = api.rpa_energy(dc, 6, om, W, [torch.tensor(V0, device=DEV)], o64, save=True)
+    g64, _, _ = api.rpa_energy_backward(dc, om, W, res["Vsave"][0], res["Csave"][0], 1.0, o64)
+    gmx, rc, st = api.rpa_energy_backward(dc, om, W, res["Vsave"][0], res["Csave"][0], 1.0,
+                                          dict(o64, precision=MIXED))
+    assert rc == 0 and st["refinements"] > 0
+    assert rel(gmx.cpu().numpy(), g64.cpu().numpy()) < 1e-8
