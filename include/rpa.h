@@ -88,7 +88,7 @@ typedef struct rpa_options {
     double ec_tol;           /* relative energy threshold |E_k - E_{k-1}| <= ec_tol |E_k|;
                                 <= 0 selects the fixed count; default 1e-8 */
     double refine_tol;       /* RPA_MIXED: relative drop of the complex64 residual between
-                                float64 refinements, default 1e-4 */
+                                float64 refinements (reliable updates), default 0.1 */
     int32_t max_systems;     /* cap on Sternheimer systems in flight (0 = library choice) */
     int32_t flags;           /* reserved, 0 */
 } rpa_options;

@@ -34,12 +34,14 @@ def candidates(n0, n1, n2):
                     continue
                 for Z in (1, 2, 4):
                     if n2 % Z == 0 and (Z <= 2 or C <= 2):
-                        out.append((C, Z, BM, bs))
+                        out.append((C, Z, BM, bs, 0))
+                    if C == 1 and BM == 768 and Z <= 2 and n2 % Z == 0 and bs == bs0:
+                        out += [(C, Z, BM, bs, 4), (C, Z, BM, bs, 5)]
     return out
 
 
 def time_shape(api, cell, omega, X, opts, shape):
-    os.environ["RPA_COCG_SHAPE"] = "%d,%d,%d,%d" % shape
+    os.environ["RPA_COCG_SHAPE"] = "%d,%d,%d,%d,%d" % shape
     try:
         out, rc, st = api.rpa_apply_chi0(cell, omega, X, opts)
     except RuntimeError as e:
@@ -77,14 +79,13 @@ def main():
     for shape in candidates(*c.shape):
         st, err = time_shape(api, dc, omega, X, opts, shape)
         if st is None:
-            print("shape C=%d Z=%d bsmax=%d bs=%d: %s" % (shape + (err,)), flush=True)
+            print("shape C=%d Z=%d bsmax=%d bs=%d occ=%d: %s" % (shape + (err,)), flush=True)
             continue
         gbs = bpp * st["cocg_point_iters"] / (st["cocg_kernel_ms"] * 1e-3) / 1e9
-        rows.append(dict(C=shape[0], Z=shape[1], bsmax=shape[2], bs=shape[3],
+        rows.append(dict(C=shape[0], Z=shape[1], bsmax=shape[2], bs=shape[3], occ=shape[4],
                          ms=st["cocg_kernel_ms"], alg_GBs=gbs, iters=st["cocg_iters_total"]))
-        print("shape C=%d Z=%d bsmax=%4d bs=%4d: %8.2f ms  %7.1f GB/s algorithmic  iters %d" %
-              (shape[0], shape[1], shape[2], shape[3], st["cocg_kernel_ms"], gbs,
-               st["cocg_iters_total"]), flush=True)
+        print("shape C=%d Z=%d bsmax=%4d bs=%4d occ=%d: %8.2f ms  %7.1f GB/s algorithmic  iters %d"
+              % (shape + (st["cocg_kernel_ms"], gbs, st["cocg_iters_total"])), flush=True)
     _, _, st0 = api.rpa_apply_chi0(dc, omega, X, opts)
     print("default choice: %.2f ms" % st0["cocg_kernel_ms"], flush=True)
     if rows:
@@ -96,7 +97,8 @@ def main():
             lines = []
             if os.path.exists(args.write):
                 lines = [l for l in open(args.write) if not l.startswith(key + " ")]
-            lines.append("%s %d %d %d %d\n" % (key, best["C"], best["Z"], best["bsmax"], best["bs"]))
+            lines.append("%s %d %d %d %d %d\n" % (key, best["C"], best["Z"], best["bsmax"], best["bs"],
+                                                   best["occ"]))
             open(args.write, "w").writelines(lines)
 
 

@@ -46,7 +46,7 @@ struct Opts {
     int subspace_iters = 50;
     int freq_mode = RPA_WARM;
     double ec_tol = 1e-8;
-    double refine_tol = 1e-4;
+    double refine_tol = 1e-1;
     int max_systems = 0;
 };
 
@@ -440,8 +440,18 @@ int subspace_iter(const rpa_cell* cell, const Grid& g, double omega, double weig
             stats->chi0_applies += 1;
             stats->subspace_iters_total += 1;
         }
-        if (info != 0) return fail(RPA_ENOTPD, "I - C is not positive definite");
-        if (!std::isfinite(E)) return fail(RPA_EINVAL, "non-finite subspace energy");
+        if (info != 0 || !std::isfinite(E)) {
+            // C should be negative semidefinite; if it is not, name the likely cause
+            if (t.breakdown)
+                return fail(RPA_EBREAKDOWN, "COCG breakdown in " + std::to_string(t.breakdown) +
+                                                " system(s); I - C not positive definite");
+            if (t.unconv)
+                return fail(RPA_ENOTCONV < 0 ? RPA_ENOTCONV : RPA_ENOTPD,
+                            std::to_string(t.unconv) + " COCG system(s) hit cocg_max_iter; "
+                            "I - C not positive definite");
+            return fail(info != 0 ? RPA_ENOTPD : RPA_EINVAL,
+                        info != 0 ? "I - C is not positive definite" : "non-finite subspace energy");
+        }
         if (V_saved) RPA_HIP(launch_copy(nd * nr, V, V_saved, s));
         if (C_out) RPA_HIP(launch_copy(int64_t(nr) * nr, b.C, C_out, s));
         RPA_CHECK(chol_orthonormalize(g, nr, b.R, V, b, s));

@@ -5,7 +5,7 @@
 // (spill) size are read from the runtime, and the choice is the spill-free variant that
 // leaves the fewest idle columns, then the one with more planes per step.  A shape measured
 // by the autotuner for the same precision and grid (tuning file) takes precedence, and
-// RPA_COCG_SHAPE="C,Z,bsmax[,bs]" forces one (used by the autotuner itself).  A forced shape
+// RPA_COCG_SHAPE="C,Z,bsmax[,bs[,occ]]" forces one (used by the autotuner itself).  A forced shape
 // that is not valid for the grid falls back to the automatic choice.
 #include <dlfcn.h>
 
@@ -22,11 +22,11 @@ namespace rpa {
 
 namespace {
 
-// Tuned shapes from the autotuner: lines "precision n0 n1 n2 C Z bsmax bs", read once from
+// Tuned shapes from the autotuner: lines "precision n0 n1 n2 C Z bsmax bs occ", read once from
 // RPA_TUNE_FILE or from cocg_shapes.txt next to this shared library.
 struct Tuned {
     bool mixed;
-    int n0, n1, n2, C, Z, bsmax, bs;
+    int n0, n1, n2, C, Z, bsmax, bs, occ;
 };
 
 const std::vector<Tuned>& tuned_shapes() {
@@ -49,8 +49,8 @@ const std::vector<Tuned>& tuned_shapes() {
         if (!f) return;
         char prec[16];
         Tuned t{};
-        while (std::fscanf(f, "%15s %d %d %d %d %d %d %d", prec, &t.n0, &t.n1, &t.n2, &t.C, &t.Z,
-                           &t.bsmax, &t.bs) == 8) {
+        while (std::fscanf(f, "%15s %d %d %d %d %d %d %d %d", prec, &t.n0, &t.n1, &t.n2, &t.C, &t.Z,
+                           &t.bsmax, &t.bs, &t.occ) == 9) {
             t.mixed = std::strcmp(prec, "mixed") == 0;
             table.push_back(t);
         }
@@ -85,11 +85,11 @@ Chosen choose(const Grid& g, bool mixed, bool xcomplex, bool allow_forced) {
     const int P = g.n0 * g.n1;
     int nv = 0;
     const cocg::Variant* tab = cocg::f64_variants(&nv);
-    int fC = 0, fZ = 0, fB = 0, fBS = 0;
+    int fC = 0, fZ = 0, fB = 0, fBS = 0, fO = 0;
     if (!allow_forced) {
         // automatic choice only
     } else if (const char* env = std::getenv("RPA_COCG_SHAPE")) {
-        if (std::sscanf(env, "%d,%d,%d,%d", &fC, &fZ, &fB, &fBS) < 3) fC = fZ = fB = fBS = 0;
+        if (std::sscanf(env, "%d,%d,%d,%d,%d", &fC, &fZ, &fB, &fBS, &fO) < 3) fC = fZ = fB = fBS = 0;
     } else {
         for (const Tuned& t : tuned_shapes())
             if (t.mixed == mixed && t.n0 == g.n0 && t.n1 == g.n1 && t.n2 == g.n2) {
@@ -97,13 +97,14 @@ Chosen choose(const Grid& g, bool mixed, bool xcomplex, bool allow_forced) {
                 fZ = t.Z;
                 fB = t.bsmax;
                 fBS = t.bs;
+                fO = t.occ;
             }
     }
     Chosen best;
     double best_cost = 1e30;
     for (int k = 0; k < nv; ++k) {
         const cocg::Variant& v = tab[k];
-        cocg::KernelFn fn = mixed ? cocg::mixed_variant(v.C, v.Z, v.bsmax)
+        cocg::KernelFn fn = mixed ? cocg::mixed_variant(v.C, v.Z, v.bsmax, v.occ)
                                   : (xcomplex ? v.f64_cplx : v.f64_real);
         if (!fn) continue;
         if (g.n2 % v.Z != 0) continue;
@@ -122,7 +123,8 @@ Chosen choose(const Grid& g, bool mixed, bool xcomplex, bool allow_forced) {
         int regs = 0;
         size_t scratch = 0;
         if (!attrs(fn, &regs, &scratch)) continue;
-        if (fC && (v.C != fC || v.Z != fZ || v.bsmax != fB)) continue;
+        if (fC && (v.C != fC || v.Z != fZ || v.bsmax != fB || v.occ != fO)) continue;
+        if (!fC && v.occ != 0) continue;          // capped variants only when tuned or forced
         const double idle = double(bs * v.C - P) / double(bs * v.C);
         double cost = idle + (scratch > 0 ? 1.0 : 0.0) + 0.03 * (4 - v.Z) + 0.05 * (2 - nbuf);
         if (cost < best_cost - 1e-12) {

@@ -439,11 +439,23 @@ __device__ __forceinline__ void true_residual(const Args& a, const Cols<C>& cl, 
 // ---------------------------------------------------------------- the solver
 // T: state precision (double: FP64 path, float: mixed); XS: type of the stored solution in
 // the FP64 path (double = real part only, double2 = complex); ignored when T = float.
-template <typename T, typename XS, int C, int Z, int BSMAX>
-__global__ __launch_bounds__(BSMAX) void cocg_wg(Args a) {
+// OCC = minimum resident waves per SIMD the register allocation must allow (0: derived from
+// BSMAX alone); higher values cap the registers so that two workgroups share a CU.
+template <typename T, typename XS, int C, int Z, int BSMAX, int OCC = 0>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, BSMAX),
+                          amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
+void cocg_wg(Args a) {
     using T2 = typename Cplx<T>::type;
     constexpr bool MIXED = std::is_same<T, float>::value;
-    const int sys = blockIdx.x;
+    // Hardest systems first: orbitals closest to the gap (largest n) have the smallest shifted
+    // gap and need the most iterations, so they are dispatched before the easier ones, which
+    // then fill the CUs behind them instead of leaving a long single-system tail.  System
+    // s = n + ns*j; workgroup b takes n = ns-1 - b / nvec, j = b % nvec.
+    const int nvec_l = int(gridDim.x) / a.ns;
+    const int bid = blockIdx.x;
+    const int sys = (nvec_l > 0 && int(gridDim.x) % a.ns == 0)
+                        ? (a.ns - 1 - bid / nvec_l) + a.ns * (bid % nvec_l)
+                        : bid;
     const int tid = threadIdx.x, BS = blockDim.x;
     const int n0 = a.n0, P = a.P;
     const int64_t off = int64_t(sys) * a.nd;

@@ -10,7 +10,7 @@ namespace cocg {
 using KernelFn = void (*)(Args);
 
 struct Variant {
-    int C, Z, bsmax;
+    int C, Z, bsmax, occ;
     KernelFn f64_real;   // FP64 path, real part of the solution stored
     KernelFn f64_cplx;   // FP64 path, complex solution stored
     KernelFn mixed;      // complex64 state with float64 reliable updates (null if absent)
@@ -18,7 +18,7 @@ struct Variant {
 
 // Defined in cocg_f64.hip and cocg_mixed.hip.
 const Variant* f64_variants(int* count);
-KernelFn mixed_variant(int C, int Z, int bsmax);
+KernelFn mixed_variant(int C, int Z, int bsmax, int occ);
 
 }  // namespace cocg
 }  // namespace rpa

@@ -191,12 +191,15 @@ def test_mixed_chi0_matches_oracle(wl0, dc0):
 
 @pytest.mark.parametrize("omega", [0.02, 8.8])
 def test_mixed_chi0_extreme_frequencies(wl0, dc0, omega):
+    # Two solutions meeting a residual tolerance tol can differ by up to cond(A) * tol
+    # (cond ~ 1e3 at omega = 0.02); the mixed path follows a different Krylov sequence from
+    # the oracle, so both solve to 1e-12 and are compared at 1e-9.
     c = wl0.cells[0]
     say("mixed chi0 omega", omega)
     U = np.random.default_rng(3).standard_normal((4, c.nd))
     out, rc, st = api.rpa_apply_chi0(dc0, omega, torch.tensor(U, device=DEV),
-                                     dict(cocg_tol=1e-10, precision=MIXED))
-    ref, _, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, omega, c.shape, c.h, 1e-10, 5000)
+                                     dict(cocg_tol=1e-12, precision=MIXED))
+    ref, _, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, omega, c.shape, c.h, 1e-12, 5000)
     assert rc == 0 and rel(out.cpu().numpy().T, ref) < 1e-9
 
 
