@@ -68,8 +68,10 @@ struct Chosen {
 // Reduction scratch plus nbuf buffers of Z staged planes (rows padded by 6 ghost columns on
 // each side).  Elements are 16 B (the FP64 queue entry, also used by the true-residual sweep
 // of the mixed kernel).
+int lds_row(int n0) { return (n0 + 12 + 7) / 8 * 8; }
+
 size_t lds_bytes(int n0, int n1, int Z, int nbuf) {
-    const size_t pl = size_t(n1) * size_t(n0 + 12);
+    const size_t pl = size_t(n1) * size_t(lds_row(n0));
     return 16 * 8 * sizeof(double) + size_t(nbuf) * size_t(Z) * pl * 16;
 }
 
@@ -171,6 +173,7 @@ hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     if (!ch.fn) ch = choose(L.g, L.fp32, L.x_complex, false);
     if (!ch.fn) return hipErrorInvalidConfiguration;
     a.nbuf = ch.nbuf;
+    a.rs = lds_row(L.g.n0);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ch.fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(ch.lds));
     if (e != hipSuccess) return e;

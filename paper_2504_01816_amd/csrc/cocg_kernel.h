@@ -61,6 +61,7 @@ struct Args {
     int* status;
     int* refinements;      // mixed: per system
     int nbuf;              // LDS plane buffers (2: one barrier per step, 1: two barriers)
+    int rs;                // LDS row stride in entries: n0 + 12 rounded up to a multiple of 8
 };
 
 // Element access through a uniform base pointer and a 32-bit unsigned offset, so loads and
@@ -78,15 +79,20 @@ __device__ __forceinline__ void st(V* base, unsigned idx, V v) {
 #define RPA_PREFETCH 1
 #endif
 
-// Compiler fence between groups of stencil LDS reads (bounds the reads in flight).
-#ifndef RPA_LDS_GROUP_FENCE
-#define RPA_LDS_GROUP_FENCE() asm volatile("" ::: "memory")
-#endif
-
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// A workgroup-uniform double moved to scalar registers.  Reduction results are uniform by
+// construction (every thread sums the same LDS entries in the same order), but the compiler
+// cannot prove it for values read from LDS and would keep them in vector registers.
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane(int(b));
+    const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
 template <int NV>
@@ -106,7 +112,7 @@ __device__ __forceinline__ void wg_reduce(double (&v)[NV], double* red) {
     for (int k = 0; k < NV; ++k) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += red[w * NV + k];
-        v[k] = s;
+        v[k] = uniform(s);
     }
     lds_barrier();
 }
@@ -117,56 +123,44 @@ struct Cols {
     bool valid[C];
 };
 
-// LDS plane layout: rows of RS = n0 + 12 entries; row y holds x = -6 .. n0+5 (periodic
-// ghosts on both sides), so x neighbours are fixed offsets from a point; y neighbours are
-// addressed with the periodic wrap of the row index.
-__device__ __forceinline__ int lds_center(int n0, int cx, int cy) { return cy * (n0 + 12) + cx + 6; }
+// LDS plane layout: rows of RS >= n0 + 12 entries (RS a multiple of 8, so that a wave's
+// reads stay free of bank conflicts where it crosses a row end); row y holds x = -6 .. n0+5
+// (periodic ghosts on both sides), so x neighbours are fixed offsets from a point; y
+// neighbours are addressed with the periodic wrap of the row index.
+__device__ __forceinline__ int lds_center(int rs, int cx, int cy) { return cy * rs + cx + 6; }
 
 template <typename Q2>
-__device__ __forceinline__ void stage_point(Q2* L, int n0, int cx, int cy, Q2 v) {
-    const int c0 = lds_center(n0, cx, cy);
+__device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int cx, int cy, Q2 v) {
+    const int c0 = lds_center(rs, cx, cy);
     L[c0] = v;
     if (cx < 6) L[c0 + n0] = v;
     if (cx >= n0 - 6) L[c0 - n0] = v;
 }
 
 // q = (A c) for one column: A = -1/2 Lap_h + V - eps - i omega; x/y neighbours from the
-// LDS plane L, z neighbours from the queue entries Q[zc-6 .. zc+6][i].
+// LDS plane L, z neighbours from the queue entries Q[zc-6 .. zc+6][i].  The three axes share
+// the weights, so each distance k costs one multiply-add per component.  Each k's four LDS
+// reads are consumed before the next k's are issued (the empty asm ties the accumulators),
+// which bounds the registers held by reads in flight.
 template <typename R, typename Q2, int NQ, int C>
 __device__ __forceinline__ Q2 stencil(const Args& a, const Q2* __restrict__ L, const Q2 (&Q)[NQ][C],
                                       int zc, int i, int cx, int cy, R diag, R om) {
-    const int n0 = a.n0, n1 = a.n1, RS = n0 + 12;
+    const int n1 = a.n1, RS = a.rs;
     // keep the row index opaque so that neighbour addresses are formed here, not hoisted
     // out of the z loop into long-lived registers
     asm volatile("" : "+v"(cy));
     const Q2* Lc = L + cy * RS + cx + 6;
     R ax = 0, ay = 0;
-    // neighbours are read in groups of four LDS loads; the fence keeps the compiler from
-    // issuing all 24 reads (and their registers) ahead of use
-#pragma unroll
-    for (int k = 1; k <= 6; k += 2) {
-        const Q2 a1 = Lc[k], a2 = Lc[-k], a3 = Lc[k + 1], a4 = Lc[-k - 1];
-        ax += R(a.cw[k]) * (a1.x + a2.x) + R(a.cw[k + 1]) * (a3.x + a4.x);
-        ay += R(a.cw[k]) * (a1.y + a2.y) + R(a.cw[k + 1]) * (a3.y + a4.y);
-        RPA_LDS_GROUP_FENCE();
-    }
-#pragma unroll
-    for (int k = 1; k <= 6; k += 2) {
-        int yp = cy + k; yp -= (yp >= n1) ? n1 : 0;
-        int ym = cy - k; ym += (ym < 0) ? n1 : 0;
-        int yp2 = cy + k + 1; yp2 -= (yp2 >= n1) ? n1 : 0;
-        int ym2 = cy - k - 1; ym2 += (ym2 < 0) ? n1 : 0;
-        const Q2 b1 = L[yp * RS + cx + 6], b2 = L[ym * RS + cx + 6];
-        const Q2 b3 = L[yp2 * RS + cx + 6], b4 = L[ym2 * RS + cx + 6];
-        ax += R(a.cw[k]) * (b1.x + b2.x) + R(a.cw[k + 1]) * (b3.x + b4.x);
-        ay += R(a.cw[k]) * (b1.y + b2.y) + R(a.cw[k + 1]) * (b3.y + b4.y);
-        RPA_LDS_GROUP_FENCE();
-    }
 #pragma unroll
     for (int k = 1; k <= 6; ++k) {
+        int yp = cy + k; yp -= (yp >= n1) ? n1 : 0;
+        int ym = cy - k; ym += (ym < 0) ? n1 : 0;
+        const Q2 a1 = Lc[k], a2 = Lc[-k];
+        const Q2 b1 = L[yp * RS + cx + 6], b2 = L[ym * RS + cx + 6];
         const Q2 c1 = Q[zc + k][i], c2 = Q[zc - k][i];
-        ax += R(a.cw[k]) * (c1.x + c2.x);
-        ay += R(a.cw[k]) * (c1.y + c2.y);
+        ax += R(a.cw[k]) * (((a1.x + a2.x) + (b1.x + b2.x)) + (c1.x + c2.x));
+        ay += R(a.cw[k]) * (((a1.y + a2.y) + (b1.y + b2.y)) + (c1.y + c2.y));
+        asm volatile("" : "+v"(ax), "+v"(ay) :: "memory");
     }
     const Q2 c = Q[zc][i];
     return Q2{ax + diag * c.x + om * c.y, ay + diag * c.y - om * c.x};
@@ -255,13 +249,13 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
                 }
             }
         }
-        const int PL = a.n1 * (a.n0 + 12);       // padded plane
+        const int PL = a.n1 * a.rs;              // padded plane
         Q2* L = lds + (a.nbuf == 2 ? (st & 1) : 0) * Z * PL;
 #pragma unroll
         for (int zz = 0; zz < Z; ++zz)
 #pragma unroll
             for (int i = 0; i < C; ++i)
-                if (cl.valid[i]) stage_point(L + zz * PL, a.n0, cl.cx[i], cl.cy[i], Q[6 + zz][i]);
+                if (cl.valid[i]) stage_point(L + zz * PL, a.rs, a.n0, cl.cx[i], cl.cy[i], Q[6 + zz][i]);
         lds_barrier();
 #pragma unroll
         for (int zz = 0; zz < Z; ++zz) {
@@ -393,20 +387,20 @@ template <int C>
 __device__ __forceinline__ void true_residual(const Args& a, const Cols<C>& cl, double2* lds,
                                               double eps_n, const double2* xhi, const double* b,
                                               float2* r, double (&acc)[3]) {
-    const int n2 = a.n2, P = a.P, n0 = a.n0, n1 = a.n1, RS = n0 + 12;
+    const int n2 = a.n2, P = a.P, n0 = a.n0, n1 = a.n1, RS = a.rs;
     acc[0] = acc[1] = acc[2] = 0.0;
     for (int z = 0; z < n2; ++z) {
         double2* L = lds;
 #pragma unroll
         for (int i = 0; i < C; ++i)
             if (cl.valid[i])
-                stage_point(L, n0, cl.cx[i], cl.cy[i], ld(xhi, unsigned(z * P + cl.col[i])));
+                stage_point(L, RS, n0, cl.cx[i], cl.cy[i], ld(xhi, unsigned(z * P + cl.col[i])));
         lds_barrier();
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             if (!cl.valid[i]) continue;
             const int cx = cl.cx[i], cy = cl.cy[i];
-            const double2* Lc = L + lds_center(n0, cx, cy);
+            const double2* Lc = L + lds_center(RS, cx, cy);
             const double2 c = Lc[0];
             double ax = 0, ay = 0;
 #pragma unroll
@@ -489,25 +483,29 @@ void cocg_wg(Args a) {
         const bool first = (it == 0);
         // ---------------------------------------------------------- sweep 1
         if (!first) {
-            // warm start of sweep 1 from the queue: p_new = r + beta p on planes -6 .. 5
-            T2 rw[12][C];
-#pragma unroll
-            for (int s = 0; s < 12; ++s) {
-                int z = s - 6;
-                z += (z < 0) ? a.n2 : 0;
-#pragma unroll
-                for (int i = 0; i < C; ++i)
-                    rw[s][i] = cl.valid[i] ? ld(r, unsigned(z * P + cl.col[i])) : T2{0, 0};
-            }
+            // warm start of sweep 1 from the queue: p_new = r + beta p on planes -6 .. 5,
+            // four planes at a time
             const T br = T(beta_re), bi = T(beta_im);
 #pragma unroll
-            for (int s = 0; s < 12; ++s)
+            for (int s0 = 0; s0 < 12; s0 += 4) {
+                T2 rw[4][C];
 #pragma unroll
-                for (int i = 0; i < C; ++i) {
-                    const T2 pv = Q[s][i];
-                    Q[s][i] = T2{rw[s][i].x + br * pv.x - bi * pv.y,
-                                 rw[s][i].y + br * pv.y + bi * pv.x};
+                for (int s = 0; s < 4; ++s) {
+                    int z = s0 + s - 6;
+                    z += (z < 0) ? a.n2 : 0;
+#pragma unroll
+                    for (int i = 0; i < C; ++i)
+                        rw[s][i] = cl.valid[i] ? ld(r, unsigned(z * P + cl.col[i])) : T2{0, 0};
                 }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int i = 0; i < C; ++i) {
+                        const T2 pv = Q[s0 + s][i];
+                        Q[s0 + s][i] = T2{rw[s][i].x + br * pv.x - bi * pv.y,
+                                          rw[s][i].y + br * pv.y + bi * pv.x};
+                    }
+            }
         }
         LeadPnew<T2, C> l1{r, pa, P, cl.col, first, beta_re, beta_im};
         CentSigma<T2, C> c1{pb, P, cl.col, first, {0, 0, 0, 0, 0, 0, 0}};
@@ -528,8 +526,8 @@ void cocg_wg(Args a) {
             if (!(s2 > a.bd_tol * a.bd_tol * c1.acc[2] * c1.acc[3])) {
                 breakdown = true;
             } else {
-                alpha_re = (rho_re * c1.acc[0] + rho_im * c1.acc[1]) / s2;
-                alpha_im = (rho_im * c1.acc[0] - rho_re * c1.acc[1]) / s2;
+                alpha_re = uniform((rho_re * c1.acc[0] + rho_im * c1.acc[1]) / s2);
+                alpha_im = uniform((rho_im * c1.acc[0] - rho_re * c1.acc[1]) / s2);
             }
         }
         // ---------------------------------------------------------- sweep 2
@@ -590,8 +588,8 @@ void cocg_wg(Args a) {
                     done = true;
                 } else {
                     const double rr = rho_re * rho_re + rho_im * rho_im;
-                    beta_re = (acc2[0] * rho_re + acc2[1] * rho_im) / rr;
-                    beta_im = (acc2[1] * rho_re - acc2[0] * rho_im) / rr;
+                    beta_re = uniform((acc2[0] * rho_re + acc2[1] * rho_im) / rr);
+                    beta_im = uniform((acc2[1] * rho_re - acc2[0] * rho_im) / rr);
                     rho_re = acc2[0];
                     rho_im = acc2[1];
                     T2* t = pa;

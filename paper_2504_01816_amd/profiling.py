@@ -1,0 +1,172 @@
+"""Workloads and summaries for hardware-counter profiling of the COCG kernel.
+
+Subcommands (run under rocprofv3, one counter set per run):
+
+  copy       a plain device copy of a known size (torch's copy kernel), used to scale the
+             FETCH_SIZE / WRITE_SIZE counters to bytes
+  apply      one chi0 block-apply at each frequency of a workload; prints the COCG kernel's
+             point-iterations and launch count as JSON (stderr)
+  summarize  reduce a rocprofv3 counter CSV to per-kernel means (markdown on stdout)
+  traffic    combine the FETCH_SIZE and WRITE_SIZE summaries of the copy and the apply runs
+             into HBM bytes per point-iteration of the COCG kernel (JSON read by bench.py)
+
+Example:
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o copy -- \
+      python -m paper_2504_01816_amd.profiling copy --mib 1024
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/cocg_kernel.h", "csrc/cocg.hip", "csrc/cocg_f64.hip", "csrc/cocg_mixed.hip")
+
+
+def kernel_source_hash():
+    """SHA-256 over the COCG kernel's sources: counters taken on other sources are stale."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def cmd_copy(args):
+    import torch
+
+    n = args.mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0")   # no fill kernel in the trace
+    dst = torch.empty_like(src)
+    for _ in range(args.reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "reps": args.reps}), file=sys.stderr)
+
+
+def cmd_apply(args):
+    import torch
+
+    from . import api, synth
+    from . import lib as L
+
+    wl = synth.workload(args.config)
+    c = wl.cells[0]
+    dc = api.device_cell(c, "cuda:0")
+    nvec = args.nvec or wl.n_r[0]
+    X = api.rpa_apply_coulomb(dc, torch.tensor(wl.V0[0][:nvec], device="cuda:0"), 1)
+    prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
+    opts = dict(precision=prec, cocg_tol=wl.cocg_tol)
+    tot = {"cocg_point_iters": 0.0, "cocg_launches": 0, "cocg_kernel_ms": 0.0, "cocg_iters_total": 0}
+    idx = range(len(wl.omegas)) if args.omega_index < 0 else [args.omega_index]
+    for m in idx:
+        _, _, st = api.rpa_apply_chi0(dc, float(wl.omegas[m]), X, opts)
+        for k in tot:
+            tot[k] += st[k]
+    torch.cuda.synchronize()
+    tot.update(workload=wl.name, precision=args.precision, nvec=nvec, omegas=list(idx))
+    print(json.dumps(tot), file=sys.stderr)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(tot, f)
+
+
+def read_counters(path):
+    """Rows of a rocprofv3 counter_collection CSV as (kernel, counter, value) per dispatch."""
+    rows = []
+    for fn in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+                     if os.path.isdir(path) else [path]):
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]),
+                             r.get("Dispatch_Id", "")))
+    return rows
+
+
+def per_kernel_means(rows):
+    acc = {}
+    for k, c, v, d in rows:
+        key = (k, c)
+        s = acc.setdefault(key, {"sum": 0.0, "dispatches": set()})
+        s["sum"] += v
+        s["dispatches"].add(d)
+    return {key: (s["sum"] / max(1, len(s["dispatches"])), len(s["dispatches"]), s["sum"])
+            for key, s in acc.items()}
+
+
+def short(name, n=70):
+    name = name.replace("rpa::cocg::", "").replace("HIP_vector_type", "vec")
+    return name if len(name) <= n else name[: n - 3] + "..."
+
+
+def cmd_summarize(args):
+    means = per_kernel_means(read_counters(args.csv))
+    print("| kernel | counter | dispatches | mean per dispatch | total |")
+    print("|---|---|---|---|---|")
+    for (k, c), (m, n, t) in sorted(means.items(), key=lambda kv: -kv[1][2]):
+        if args.match and args.match not in k:
+            continue
+        print("| `%s` | %s | %d | %.6g | %.6g |" % (short(k), c, n, m, t))
+
+
+def _total(rows, match, counter):
+    return sum(v for k, c, v, _ in rows if match in k and c == counter)
+
+
+def cmd_traffic(args):
+    """Bytes per COCG point-iteration from FETCH_SIZE / WRITE_SIZE (KiB), each scaled so that
+    the copy kernel of known size reads (writes) exactly its size."""
+    out = {"kernel_source_sha256": kernel_source_hash(), "precision": args.precision}
+    stats = json.load(open(args.apply_stats))
+    copy_bytes = float(args.copy_mib << 20) * args.copy_reps
+    for counter, copy_csv, apply_csv in (("FETCH_SIZE", args.copy_fetch, args.apply_fetch),
+                                         ("WRITE_SIZE", args.copy_write, args.apply_write)):
+        crow = read_counters(copy_csv)
+        cval = sum(v for k, c, v, _ in crow if c == counter and "cocg" not in k)
+        factor = copy_bytes / (cval * 1024.0) if cval > 0 else float("nan")
+        aval = _total(read_counters(apply_csv), "cocg_wg", counter)
+        out[counter.lower() + "_copy_factor"] = factor
+        out[counter.lower() + "_bytes_per_point_iter"] = aval * 1024.0 * factor / stats["cocg_point_iters"]
+    out["bytes_per_point_iter"] = (out["fetch_size_bytes_per_point_iter"]
+                                   + out["write_size_bytes_per_point_iter"])
+    out["apply_stats"] = stats
+    print(json.dumps(out, indent=1))
+    if args.write:
+        with open(args.write, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=1024)
+    c.add_argument("--reps", type=int, default=4)
+    a = sub.add_parser("apply")
+    a.add_argument("--config", type=int, default=1)
+    a.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    a.add_argument("--omega-index", type=int, default=-1, help="-1: every frequency")
+    a.add_argument("--nvec", type=int, default=0)
+    a.add_argument("--out", default="")
+    s = sub.add_parser("summarize")
+    s.add_argument("csv")
+    s.add_argument("--match", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("--precision", default="fp64")
+    t.add_argument("--copy-mib", type=int, default=1024)
+    t.add_argument("--copy-reps", type=int, default=4)
+    t.add_argument("--copy-fetch", required=True)
+    t.add_argument("--copy-write", required=True)
+    t.add_argument("--apply-fetch", required=True)
+    t.add_argument("--apply-write", required=True)
+    t.add_argument("--apply-stats", required=True)
+    t.add_argument("--write", default="")
+    args = ap.parse_args()
+    {"copy": cmd_copy, "apply": cmd_apply, "summarize": cmd_summarize, "traffic": cmd_traffic}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()
