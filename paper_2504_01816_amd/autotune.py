@@ -35,8 +35,6 @@ def candidates(n0, n1, n2):
                 for Z in (1, 2, 4):
                     if n2 % Z == 0 and (Z <= 2 or C <= 2):
                         out.append((C, Z, BM, bs, 0))
-                    if C == 1 and BM == 768 and Z <= 2 and n2 % Z == 0 and bs == bs0:
-                        out += [(C, Z, BM, bs, 4), (C, Z, BM, bs, 5)]
     return out
 
 

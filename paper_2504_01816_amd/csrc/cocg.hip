@@ -65,13 +65,13 @@ struct Chosen {
     size_t lds = 0;
 };
 
-// Reduction scratch plus nbuf buffers of Z staged planes (rows padded by 6 ghost columns on
+// Reduction scratch plus nbuf buffers of Z staged planes (6 ghost columns and 6 ghost rows on
 // each side).  Elements are 16 B (the FP64 queue entry, also used by the true-residual sweep
 // of the mixed kernel).
 int lds_row(int n0) { return (n0 + 12 + 7) / 8 * 8; }
 
 size_t lds_bytes(int n0, int n1, int Z, int nbuf) {
-    const size_t pl = size_t(n1) * size_t(lds_row(n0));
+    const size_t pl = size_t(n1 + 12) * size_t(lds_row(n0));
     return 16 * 8 * sizeof(double) + size_t(nbuf) * size_t(Z) * pl * 16;
 }
 

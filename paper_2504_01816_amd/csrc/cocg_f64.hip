@@ -10,10 +10,7 @@ namespace cocg {
 #define RPA_VZ(CC, ZZ) RPA_V(CC, ZZ, 512, 0), RPA_V(CC, ZZ, 768, 0), RPA_V(CC, ZZ, 1024, 0)
 static const Variant kTable[] = {RPA_VZ(1, 1), RPA_VZ(1, 2), RPA_VZ(1, 4),
                                  RPA_VZ(2, 1), RPA_VZ(2, 2), RPA_VZ(2, 4),
-                                 RPA_VZ(3, 1), RPA_VZ(3, 2),
-                                 // register-capped variants: two workgroups per CU
-                                 RPA_V(1, 1, 768, 4), RPA_V(1, 2, 768, 4), RPA_V(1, 1, 768, 5),
-                                 RPA_V(1, 2, 768, 5)};
+                                 RPA_VZ(3, 1), RPA_VZ(3, 2)};
 #undef RPA_VZ
 #undef RPA_V
 

@@ -79,6 +79,11 @@ __device__ __forceinline__ void st(V* base, unsigned idx, V v) {
 #define RPA_PREFETCH 1
 #endif
 
+// Stencil distances whose LDS reads may be in flight together (4 reads each).
+#ifndef RPA_STENCIL_GROUP
+#define RPA_STENCIL_GROUP 1
+#endif
+
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -123,18 +128,22 @@ struct Cols {
     bool valid[C];
 };
 
-// LDS plane layout: rows of RS >= n0 + 12 entries (RS a multiple of 8, so that a wave's
-// reads stay free of bank conflicts where it crosses a row end); row y holds x = -6 .. n0+5
-// (periodic ghosts on both sides), so x neighbours are fixed offsets from a point; y
-// neighbours are addressed with the periodic wrap of the row index.
-__device__ __forceinline__ int lds_center(int rs, int cx, int cy) { return cy * rs + cx + 6; }
+// LDS plane layout: n1 + 12 rows of RS >= n0 + 12 entries (RS a multiple of 8, so that a
+// wave's reads stay free of bank conflicts where it crosses a row end).  Row y + 6 holds
+// x = -6 .. n0+5 of grid row y, for y = -6 .. n1+5: the 6 ghost columns on each side and the
+// 6 ghost rows above and below hold the periodic images, so every neighbour of a point is a
+// fixed offset from it (+-k along x, +-k RS along y) and no wrap is computed in the stencil.
+// Ghost rows carry only the real columns (the stencil has no diagonal terms).
+__device__ __forceinline__ int lds_center(int rs, int cx, int cy) { return (cy + 6) * rs + cx + 6; }
 
 template <typename Q2>
-__device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int cx, int cy, Q2 v) {
+__device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int n1, int cx, int cy, Q2 v) {
     const int c0 = lds_center(rs, cx, cy);
     L[c0] = v;
     if (cx < 6) L[c0 + n0] = v;
     if (cx >= n0 - 6) L[c0 - n0] = v;
+    if (cy < 6) L[c0 + n1 * rs] = v;
+    if (cy >= n1 - 6) L[c0 - n1 * rs] = v;
 }
 
 // q = (A c) for one column: A = -1/2 Lap_h + V - eps - i omega; x/y neighbours from the
@@ -145,29 +154,25 @@ __device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int cx, int c
 template <typename R, typename Q2, int NQ, int C>
 __device__ __forceinline__ Q2 stencil(const Args& a, const Q2* __restrict__ L, const Q2 (&Q)[NQ][C],
                                       int zc, int i, int cx, int cy, R diag, R om) {
-    const int n1 = a.n1, RS = a.rs;
-    // keep the row index opaque so that neighbour addresses are formed here, not hoisted
-    // out of the z loop into long-lived registers
-    asm volatile("" : "+v"(cy));
-    const Q2* Lc = L + cy * RS + cx + 6;
+    const int RS = a.rs;
+    const Q2* Lc = L + lds_center(RS, cx, cy);
     R ax = 0, ay = 0;
 #pragma unroll
     for (int k = 1; k <= 6; ++k) {
-        int yp = cy + k; yp -= (yp >= n1) ? n1 : 0;
-        int ym = cy - k; ym += (ym < 0) ? n1 : 0;
         const Q2 a1 = Lc[k], a2 = Lc[-k];
-        const Q2 b1 = L[yp * RS + cx + 6], b2 = L[ym * RS + cx + 6];
+        const Q2 b1 = Lc[k * RS], b2 = Lc[-k * RS];
         const Q2 c1 = Q[zc + k][i], c2 = Q[zc - k][i];
         ax += R(a.cw[k]) * (((a1.x + a2.x) + (b1.x + b2.x)) + (c1.x + c2.x));
         ay += R(a.cw[k]) * (((a1.y + a2.y) + (b1.y + b2.y)) + (c1.y + c2.y));
-        asm volatile("" : "+v"(ax), "+v"(ay) :: "memory");
+        if (k % RPA_STENCIL_GROUP == 0) asm volatile("" : "+v"(ax), "+v"(ay) :: "memory");
     }
     const Q2 c = Q[zc][i];
     return Q2{ax + diag * c.x + om * c.y, ay + diag * c.y - om * c.x};
 }
 
-// Generic z-march: lead.load(z, i) fetches what the queue entry of plane z needs,
-// lead.make(buf) turns it into the queue value; cent.load(z, i) fetches what the centre
+// Generic z-march: lead.load(z, i, first) fetches what the queue entry of plane z needs
+// (first: the plane's centre step has not run yet in this sweep), lead.make(buf) turns it
+// into the queue value; cent.load(z, i) fetches what the centre
 // step needs, cent.finish(buf, z, i, c, q) consumes the stencil result.  Loads for step
 // s+1 are issued before step s computes.
 // Q is the caller's queue.  With warm = true it already holds planes -6 .. 5 (mod n2) of the
@@ -190,7 +195,7 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
             z += (z < 0) ? n2 : 0;
 #pragma unroll
             for (int i = 0; i < C; ++i)
-                Q[12 + zz][i] = cl.valid[i] ? lead.make(lead.load(z, i)) : Q2{0, 0};
+                Q[12 + zz][i] = cl.valid[i] ? lead.make(lead.load(z, i, true)) : Q2{0, 0};
         }
 #pragma unroll
         for (int s = 0; s < 12; ++s)
@@ -204,7 +209,7 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             if (cl.valid[i]) {
-                LB[zz][i] = lead.load(z, i);
+                LB[zz][i] = lead.load(z, i, true);
                 CB[zz][i] = cent.load(zz, i);
             }
         }
@@ -217,12 +222,12 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
         if (!RPA_PREFETCH && st > 0) {
 #pragma unroll
             for (int zz = 0; zz < Z; ++zz) {
-                int z = zo + 6 + zz;
-                z -= (z >= n2) ? n2 : 0;
+                const int zu = zo + 6 + zz;
+                const int z = zu - ((zu >= n2) ? n2 : 0);
 #pragma unroll
                 for (int i = 0; i < C; ++i)
                     if (cl.valid[i]) {
-                        LB[zz][i] = lead.load(z, i);
+                        LB[zz][i] = lead.load(z, i, zu < n2 || zu - n2 >= zo);
                         CB[zz][i] = cent.load(zo + zz, i);
                     }
             }
@@ -237,25 +242,27 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
         if (RPA_PREFETCH && st + 1 < nsteps) {
 #pragma unroll
             for (int zz = 0; zz < Z; ++zz) {
-                int z = zo + Z + 6 + zz;
-                z -= (z >= n2) ? n2 : 0;
-                z -= (z >= n2) ? n2 : 0;
+                const int zu = zo + Z + 6 + zz;          // < 2 n2 since n2 >= 12, Z <= 4
+                const int z = zu - ((zu >= n2) ? n2 : 0);
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     if (cl.valid[i]) {
-                        LB[zz][i] = lead.load(z, i);
+                        // planes below zo have had their centre step; this step's
+                        // centres run after these loads are issued
+                        LB[zz][i] = lead.load(z, i, zu < n2 || zu - n2 >= zo);
                         CB[zz][i] = cent.load(zo + Z + zz, i);
                     }
                 }
             }
         }
-        const int PL = a.n1 * a.rs;              // padded plane
+        const int PL = (a.n1 + 12) * a.rs;       // plane with ghost rows and columns
         Q2* L = lds + (a.nbuf == 2 ? (st & 1) : 0) * Z * PL;
 #pragma unroll
         for (int zz = 0; zz < Z; ++zz)
 #pragma unroll
             for (int i = 0; i < C; ++i)
-                if (cl.valid[i]) stage_point(L + zz * PL, a.rs, a.n0, cl.cx[i], cl.cy[i], Q[6 + zz][i]);
+                if (cl.valid[i])
+                    stage_point(L + zz * PL, a.rs, a.n0, a.n1, cl.cx[i], cl.cy[i], Q[6 + zz][i]);
         lds_barrier();
 #pragma unroll
         for (int zz = 0; zz < Z; ++zz) {
@@ -284,7 +291,7 @@ template <typename T2, int C>
 struct LeadPnew {
     struct Buf { T2 r, p; };
     const T2* r; const T2* pa; int P; const int* col; bool first; double dbr, dbi;
-    __device__ Buf load(int z, int i) const {
+    __device__ Buf load(int z, int i, bool) const {
         const unsigned idx = unsigned(z * P + col[i]);
         Buf b;
         b.r = ld(r, idx);
@@ -322,7 +329,7 @@ template <typename T2>
 struct LeadLoad {
     using Buf = T2;
     const T2* v; int P; const int* col;
-    __device__ Buf load(int z, int i) const { return ld(v, unsigned(z * P + col[i])); }
+    __device__ Buf load(int z, int i, bool) const { return ld(v, unsigned(z * P + col[i])); }
     __device__ T2 make(const Buf& b) const { return b; }
 };
 // x stored as XS (double: real part only, double2: complex FP64, float2: complex64 x_lo)
@@ -361,8 +368,44 @@ struct CentUpdate {
 };
 
 // ---------------------------------------------------------------- reliable update (mixed)
-// pointwise x_hi <- x_hi + x_lo (FP64) over the thread's own columns, so that every global
-// address keeps a single reader and writer
+// One z-march in float64 over x_hi: the lead folds the pending complex64 partial solution
+// into x_hi (x_hi + x_lo) for planes whose centre step has not run yet, and reads the stored
+// x_hi for planes already written back (the periodic wrap at the end of the sweep); the
+// centre step stores the folded x_hi and the true residual r = b - A x_hi (complex64), and
+// accumulates r^T r and |r|^2.  Every address is read and written by its own thread only.
+struct LeadFold {
+    struct Buf { double2 h; float2 l; bool fold; };
+    const double2* xhi; const float2* xlo; int P; const int* col; bool xhi_zero;
+    __device__ Buf load(int z, int i, bool first) const {
+        const unsigned idx = unsigned(z * P + col[i]);
+        Buf b;
+        b.fold = first;
+        b.h = (xhi_zero && first) ? double2{0.0, 0.0} : ld(xhi, idx);
+        b.l = first ? ld(xlo, idx) : float2{0.0f, 0.0f};
+        return b;
+    }
+    __device__ double2 make(const Buf& b) const {
+        return double2{b.h.x + double(b.l.x), b.h.y + double(b.l.y)};
+    }
+};
+struct CentResid {
+    using Buf = double;
+    double2* xhi; const double* b; float2* r; int P; const int* col;
+    double acc[3];   // rho re/im, |r|^2
+    __device__ Buf load(int z, int i) const { return ld(b, unsigned(z * P + col[i])); }
+    __device__ void finish(const Buf& bv, int z, int i, double2 c, double2 q) {
+        const unsigned idx = unsigned(z * P + col[i]);
+        st(xhi, idx, c);
+        const float2 rv = float2{float(bv - q.x), float(-q.y)};
+        st(r, idx, rv);
+        acc[0] += double(rv.x) * rv.x - double(rv.y) * rv.y;
+        acc[1] += 2.0 * double(rv.x) * rv.y;
+        acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+    }
+};
+
+// x_hi <- x_hi + x_lo over the thread's own columns (a solve that stops without a final
+// reliable update: iteration cap or breakdown)
 template <int C>
 __device__ __forceinline__ void fold_xlo(const Args& a, const int (&col)[C], const bool (&valid)[C],
                                          double2* xhi, const float2* xlo, bool xhi_zero) {
@@ -377,56 +420,6 @@ __device__ __forceinline__ void fold_xlo(const Args& a, const int (&col)[C], con
             h.y += double(l.y);
             st(xhi, idx, h);
         }
-    }
-}
-// True residual r = b - A x_hi in float64, stored as complex64 (reliable update).  This
-// sweep runs once per refinement, so it keeps no register queue: the z neighbours of x_hi
-// are read straight from global memory (each thread reads only its own columns), the x
-// and y neighbours come from the LDS plane.  Returns rho = r^T r and |r|^2 in acc.
-template <int C>
-__device__ __forceinline__ void true_residual(const Args& a, const Cols<C>& cl, double2* lds,
-                                              double eps_n, const double2* xhi, const double* b,
-                                              float2* r, double (&acc)[3]) {
-    const int n2 = a.n2, P = a.P, n0 = a.n0, n1 = a.n1, RS = a.rs;
-    acc[0] = acc[1] = acc[2] = 0.0;
-    for (int z = 0; z < n2; ++z) {
-        double2* L = lds;
-#pragma unroll
-        for (int i = 0; i < C; ++i)
-            if (cl.valid[i])
-                stage_point(L, RS, n0, cl.cx[i], cl.cy[i], ld(xhi, unsigned(z * P + cl.col[i])));
-        lds_barrier();
-#pragma unroll
-        for (int i = 0; i < C; ++i) {
-            if (!cl.valid[i]) continue;
-            const int cx = cl.cx[i], cy = cl.cy[i];
-            const double2* Lc = L + lds_center(RS, cx, cy);
-            const double2 c = Lc[0];
-            double ax = 0, ay = 0;
-#pragma unroll
-            for (int k = 1; k <= 6; ++k) {
-                int yp = cy + k; yp -= (yp >= n1) ? n1 : 0;
-                int ym = cy - k; ym += (ym < 0) ? n1 : 0;
-                int zp = z + k; zp -= (zp >= n2) ? n2 : 0;
-                int zm = z - k; zm += (zm < 0) ? n2 : 0;
-                const double2 a1 = Lc[k], a2 = Lc[-k];
-                const double2 b1 = L[yp * RS + cx + 6], b2 = L[ym * RS + cx + 6];
-                const double2 c1 = ld(xhi, unsigned(zp * P + cl.col[i]));
-                const double2 c2 = ld(xhi, unsigned(zm * P + cl.col[i]));
-                ax += a.cw[k] * ((a1.x + a2.x) + (b1.x + b2.x) + (c1.x + c2.x));
-                ay += a.cw[k] * ((a1.y + a2.y) + (b1.y + b2.y) + (c1.y + c2.y));
-            }
-            const unsigned idx = unsigned(z * P + cl.col[i]);
-            const double diag = a.cw[0] + ld(a.vloc, idx) - eps_n;
-            const double qx = ax + diag * c.x + a.omega * c.y;
-            const double qy = ay + diag * c.y - a.omega * c.x;
-            const float2 rv = float2{float(ld(b, idx) - qx), float(-qy)};
-            st(r, idx, rv);
-            acc[0] += double(rv.x) * rv.x - double(rv.y) * rv.y;
-            acc[1] += 2.0 * double(rv.x) * rv.y;
-            acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
-        }
-        lds_barrier();                    // one buffer: all reads done before the next plane
     }
 }
 
@@ -559,17 +552,18 @@ void cocg_wg(Args a) {
             if constexpr (MIXED) {
                 // reliable update when the complex64 residual fell by refine_tol or hit tol
                 if (acc2[2] <= a.tol2 * bb || acc2[2] <= a.refine2 * rr_ref) {
-                    fold_xlo<C>(a, cl.col, cl.valid, reinterpret_cast<double2*>(a.x) + off,
-                                reinterpret_cast<const float2*>(a.xlo) + off, xhi_zero);
+                    double2 Qd[12 + 1][C];
+                    LeadFold lf{reinterpret_cast<const double2*>(a.x) + off,
+                                reinterpret_cast<const float2*>(a.xlo) + off, P, cl.col, xhi_zero};
+                    CentResid cr{reinterpret_cast<double2*>(a.x) + off, a.b + off,
+                                 reinterpret_cast<float2*>(r), P, cl.col, {0, 0, 0}};
+                    march<double, double2, C, 1>(a, cl, reinterpret_cast<double2*>(planes), eps_n,
+                                                 lf, cr, Qd, false);
+                    wg_reduce<3>(cr.acc, red);
                     xhi_zero = false;
                     xlo_zero = true;
                     ++nref;
-                    double acc3[3];
-                    true_residual<C>(a, cl, reinterpret_cast<double2*>(planes), eps_n,
-                                     reinterpret_cast<const double2*>(a.x) + off, a.b + off,
-                                     reinterpret_cast<float2*>(r), acc3);
-                    wg_reduce<3>(acc3, red);
-                    acc2[0] = acc3[0]; acc2[1] = acc3[1]; acc2[2] = acc3[2];
+                    acc2[0] = cr.acc[0]; acc2[1] = cr.acc[1]; acc2[2] = cr.acc[2];
                     rr_ref = acc2[2];
                     conv = acc2[2] <= a.tol2 * bb;
                 }

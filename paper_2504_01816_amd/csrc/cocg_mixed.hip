@@ -11,7 +11,6 @@ KernelFn mixed_variant(int C, int Z, int bsmax, int occ) {
 #define RPA_CZ(CC, ZZ) RPA_CASE(CC, ZZ, 512, 0) RPA_CASE(CC, ZZ, 768, 0) RPA_CASE(CC, ZZ, 1024, 0)
     RPA_CZ(1, 1) RPA_CZ(1, 2) RPA_CZ(1, 4) RPA_CZ(2, 1) RPA_CZ(2, 2) RPA_CZ(2, 4)
     RPA_CZ(3, 1) RPA_CZ(3, 2)
-    RPA_CASE(1, 1, 768, 4) RPA_CASE(1, 2, 768, 4) RPA_CASE(1, 1, 768, 5) RPA_CASE(1, 2, 768, 5)
 #undef RPA_CZ
 #undef RPA_CASE
     return nullptr;
