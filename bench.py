@@ -41,8 +41,24 @@ def parse():
     return ap.parse_args()
 
 
+def cocg_traffic(workload, precision, point_iters_per_launch):
+    """HBM bytes per COCG launch from the committed FETCH_SIZE / WRITE_SIZE measurement
+    (bytes per point-iteration, copy-kernel scaled) times this run's point-iterations per
+    launch; None when the kernel sources changed since the counters were taken."""
+    from paper_2504_01816_amd import profiling
+
+    path = os.path.join(ROOT, "profiles", "cocg_wg_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    sha = profiling.kernel_source_hash()
+    for e in json.load(open(path))["entries"]:
+        if e["precision"] == precision and e["workload"] == workload and e["kernel_source_sha256"] == sha:
+            return e["bytes_per_point_iter"] * point_iters_per_launch, e["bytes_per_point_iter"]
+    return None, None
+
+
 def cpu_baseline(wl):
-    """Oracle (as written, single BLAS thread) on one trial vector at three frequencies."""
+    """Oracle (as written, single BLAS thread) on two trial vectors at every frequency."""
     from threadpoolctl import threadpool_limits
 
     from oracle import chi0 as ochi0
@@ -50,8 +66,9 @@ def cpu_baseline(wl):
 
     c = wl.cells[0]
     nr = wl.n_r[0]
-    pick = [0, len(wl.omegas) // 2, len(wl.omegas) - 1]
-    V = wl.V0[0][:1].T.copy()
+    pick = list(range(len(wl.omegas)))
+    nv = 2
+    V = wl.V0[0][:nv].T.copy()
     times = []
     with threadpool_limits(1):
         for m in pick:
@@ -60,14 +77,14 @@ def cpu_baseline(wl):
             D, _, _ = ochi0.chi0_apply(U, c.vloc, c.psi.T, c.eps, float(wl.omegas[m]), c.shape, c.h,
                                        wl.cocg_tol, 5000)
             ocoul.nu_apply(D, c.shape, c.h, 1)
-            times.append(time.perf_counter() - t0)
+            times.append((time.perf_counter() - t0) / nv)
     per_apply = nr * float(np.mean(times))
     return {"value": 1.0 / per_apply, "unit": "chi0 block-applies/s", "cores": 1,
             "kind": "oracle",
-            "sample": "1 of %d trial vectors (%d of %d Sternheimer systems) at omega = %s; "
-                      "block-apply time = %d x mean per-vector time %.2f s"
-                      % (nr, c.n_occ, c.n_occ * nr,
-                         ", ".join("%.4g" % wl.omegas[m] for m in pick), nr, float(np.mean(times)))}
+            "sample": "%d of %d trial vectors (%d of %d Sternheimer systems, nu^1/2 both sides) "
+                      "at each of the %d frequencies; block-apply time = %d x mean per-vector "
+                      "time %.2f s" % (nv, nr, nv * c.n_occ, c.n_occ * nr, len(pick), nr,
+                                       float(np.mean(times)))}
 
 
 def main():
@@ -144,6 +161,8 @@ def main():
     launches = sum(s["launches"] for s in steps)
     alg = ALG_BYTES[args.precision] * pit
     achieved = alg / (cocg_ms * 1e-3) / 1e9 if cocg_ms > 0 else 0.0
+    avg_ms = cocg_ms / max(1, launches)
+    traffic, tb = cocg_traffic(wl.name, args.precision, pit / max(1, launches))
     out = {
         "metric": "chi0 block-applies/s and time-to-E_c, FP32-refined batched vs FP64, 1 GPU",
         "value": applies / T,
@@ -163,9 +182,11 @@ def main():
         "subspace_iters": steps[-1]["iters"],
         "chi0_applies_per_step": applies / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "cocg_wg (batched COCG, one workgroup per system)",
-                     "launches": launches, "avg_launch_ms": cocg_ms / max(1, launches),
+                     "launches": launches, "avg_launch_ms": avg_ms,
+                     "traffic_bytes_per_point_iter": tb,
+                     "traffic_GBs": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
                      "alg_bytes_per_point_iter": ALG_BYTES[args.precision],
                      "cocg_share_of_step": cocg_ms * 1e-3 / T},
     }

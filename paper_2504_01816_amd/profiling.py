@@ -7,6 +7,7 @@ Subcommands (run under rocprofv3, one counter set per run):
   apply      one chi0 block-apply at each frequency of a workload; prints the COCG kernel's
              point-iterations and launch count as JSON (stderr)
   summarize  reduce a rocprofv3 counter CSV to per-kernel means (markdown on stdout)
+  kstats     a rocprofv3 --stats kernel summary as a markdown table
   traffic    combine the FETCH_SIZE and WRITE_SIZE summaries of the copy and the apply runs
              into HBM bytes per point-iteration of the COCG kernel (JSON read by bench.py)
 
@@ -64,6 +65,9 @@ def cmd_apply(args):
     idx = range(len(wl.omegas)) if args.omega_index < 0 else [args.omega_index]
     for m in idx:
         _, _, st = api.rpa_apply_chi0(dc, float(wl.omegas[m]), X, opts)
+        print("omega %.4g: %.2f ms, iterations %d (max %d), reliable updates %d" % (
+            wl.omegas[m], st["cocg_kernel_ms"], st["cocg_iters_total"], st["cocg_iters_max"],
+            st["refinements"]), file=sys.stderr)
         for k in tot:
             tot[k] += st[k]
     torch.cuda.synchronize()
@@ -112,6 +116,22 @@ def cmd_summarize(args):
         print("| `%s` | %s | %d | %.6g | %.6g |" % (short(k), c, n, m, t))
 
 
+def cmd_kstats(args):
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
+    fn = args.csv
+    if os.path.isdir(fn):
+        fn = sorted(glob.glob(os.path.join(fn, "**", "*kernel_stats.csv"), recursive=True))[0]
+    with open(fn) as f:
+        rows = list(csv.DictReader(f))
+    print("| kernel | calls | total ms | average ms | min ms | max ms | share |")
+    print("|---|---|---|---|---|---|---|")
+    for r in rows[: args.top]:
+        print("| `%s` | %s | %.3f | %.4f | %.4f | %.4f | %.2f%% |" % (
+            short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6, float(r["MaxNs"]) / 1e6,
+            float(r["Percentage"])))
+
+
 def _total(rows, match, counter):
     return sum(v for k, c, v, _ in rows if match in k and c == counter)
 
@@ -154,6 +174,9 @@ def main():
     s = sub.add_parser("summarize")
     s.add_argument("csv")
     s.add_argument("--match", default="")
+    k = sub.add_parser("kstats")
+    k.add_argument("csv")
+    k.add_argument("--top", type=int, default=25)
     t = sub.add_parser("traffic")
     t.add_argument("--precision", default="fp64")
     t.add_argument("--copy-mib", type=int, default=1024)
@@ -165,7 +188,8 @@ def main():
     t.add_argument("--apply-stats", required=True)
     t.add_argument("--write", default="")
     args = ap.parse_args()
-    {"copy": cmd_copy, "apply": cmd_apply, "summarize": cmd_summarize, "traffic": cmd_traffic}[args.cmd](args)
+    {"copy": cmd_copy, "apply": cmd_apply, "summarize": cmd_summarize, "kstats": cmd_kstats,
+     "traffic": cmd_traffic}[args.cmd](args)
 
 
 if __name__ == "__main__":
