@@ -59,7 +59,8 @@ extern "C" {
 #define RPA_MIXED         1   /* COCG state in complex64 with float64 residual refinement */
 
 #define RPA_WARM          0   /* Sec. 3: the subspace of one frequency starts the next */
-#define RPA_INDEPENDENT   1   /* every frequency starts from V0 (frequencies independent) */
+#define RPA_INDEPENDENT   1   /* every frequency starts from V0; all frequencies still
+                                 iterating share one batched chi0 launch per iteration */
 
 /* Operation selectors for rpa_workspace_size(). */
 #define RPA_OP_COULOMB    0
@@ -124,7 +125,8 @@ int rpa_default_options(rpa_options* opt);
  *   ncell   number of cells (1 except for RPA_OP_ENERGY)
  *   cells   host array of ncell cells (only n, n_occ and h are read)
  *   nvec    host array of ncell block widths: nvec for COULOMB/CHI0, N_r otherwise
- *   nfreq   number of frequencies (ENERGY, BACKWARD; ignored otherwise)
+ *   nfreq   number of frequencies (BACKWARD, and ENERGY with RPA_INDEPENDENT, whose
+ *           workspace holds every frequency's block; ignored otherwise)
  *   opt     options (NULL = defaults)
  *   bytes   host out
  */
@@ -183,7 +185,12 @@ int rpa_subspace_iter(const rpa_cell* cell, double omega, double weight, int32_t
  * first, as in Algorithm 1), per-frequency subspace iteration as in rpa_subspace_iter,
  * E_c = sum_m E_{c,m}.  The start block V0 of each cell is orthonormalised once (Cholesky
  * step) and then used by the first frequency (RPA_WARM) or by every frequency
- * (RPA_INDEPENDENT).
+ * (RPA_INDEPENDENT).  In RPA_INDEPENDENT mode the frequencies advance together: each
+ * subspace iteration packs the blocks of every frequency still iterating side by side and
+ * applies chi0 to all of them in one batched COCG launch (each Sternheimer system with its
+ * own shift), then the projection, energy and Cholesky-QR run per frequency; a frequency
+ * leaves the batch when its own stopping test holds.  Per frequency the result equals the
+ * warm-driver recurrence started from V0.
  *   omega, weight  host, nfreq each, omega > 0
  *   nr             host, ncell subspace sizes
  *   V0             host array of ncell device pointers, N_d x nr each (not modified)

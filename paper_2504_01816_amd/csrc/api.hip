@@ -149,7 +149,24 @@ struct Chi0Buf {
     void* xlo;      // mixed only
     double* b;      // mixed only
     int *iters, *status, *refine;
+    double* omega_v;  // per trial vector of a chunk: its frequency
+    int* order;       // per system of a chunk: dispatch order
     double2* dbuf;  // backward only
+};
+
+// Host side of a chi0 apply: the frequency of every trial vector, and per system (n + ns j
+// over the whole apply) the iteration count of the previous apply of the same block, used to
+// dispatch the longest solves first (-1: unknown).  Staging vectors stay alive until the
+// stream synchronisation in tally().
+struct Chi0Host {
+    std::vector<double> omega;
+    std::vector<int> hint;
+    std::vector<double> om_chunk;
+    std::vector<int> order, it, st, rf;
+    void reset(int ns, int nvec, double w) {
+        omega.assign(nvec, w);
+        hint.assign(size_t(ns) * nvec, -1);
+    }
 };
 
 int chunk_vectors(int ns, int nvec, const Opts& o) {
@@ -187,6 +204,8 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     b.iters = cv.take<int>(S);
     b.status = cv.take<int>(S);
     b.refine = cv.take<int>(S);
+    b.omega_v = cv.take<double>(b.chunk);
+    b.order = cv.take<int>(S);
     b.dbuf = with_d ? cv.take<double2>(size_t(ns) * S) : nullptr;
 }
 
@@ -231,6 +250,39 @@ void carve_energy(Carver& cv, const Grid& g, int ns, int nr, const Opts& o, Ener
     carve_sub(cv, g, ns, nr, o, b.sb);
     b.Vstart = cv.take<double>(size_t(g.nd()) * nr);
     b.Vcur = cv.take<double>(size_t(g.nd()) * nr);
+}
+
+// Independent frequencies batched: the blocks of all frequencies still iterating are packed
+// side by side and go through one chi0 apply per subspace iteration.
+struct BatchBuf {
+    CoulombBuf cb;
+    Chi0Buf xb;
+    double *Vstart, *Vall, *P, *U, *D, *R;   // N_d x nr (Vstart), N_d x (nf nr) (the others)
+    double *C, *M, *L, *T;                   // nr x nr per frequency
+    double *part, *ework, *escal;
+    int* info;
+    int gsplit;
+};
+void carve_batch(Carver& cv, const Grid& g, int ns, int nr, int nf, const Opts& o, BatchBuf& b) {
+    const int nall = nr * nf;
+    carve_coulomb(cv, g, nall, b.cb);
+    carve_chi0(cv, g, ns, nall, o, false, false, b.xb);
+    const size_t blk = size_t(g.nd()) * nr, sq = size_t(nr) * nr;
+    b.Vstart = cv.take<double>(blk);
+    b.Vall = cv.take<double>(blk * nf);
+    b.P = cv.take<double>(blk * nf);
+    b.U = cv.take<double>(blk * nf);
+    b.D = cv.take<double>(blk * nf);
+    b.R = cv.take<double>(blk * nf);
+    b.C = cv.take<double>(sq * nf);
+    b.M = cv.take<double>(sq * nf);
+    b.L = cv.take<double>(sq * nf);
+    b.T = cv.take<double>(sq * nf);
+    b.gsplit = gram_split(g.nd(), nr);
+    b.part = cv.take<double>(size_t(b.gsplit) * sq);
+    b.ework = cv.take<double>(2 * sq);
+    b.escal = cv.take<double>(8 * size_t(nf));
+    b.info = cv.take<int>(8 * size_t(nf));
 }
 
 struct BackBuf {
@@ -291,12 +343,15 @@ int timer_events(hipEvent_t* a, hipEvent_t* b) {
     return RPA_OK;
 }
 
-int tally(const Chi0Buf& b, int S, int64_t nd, SolveTally& t, hipStream_t s) {
-    std::vector<int> it(S), st(S), rf(S, 0);
-    RPA_HIP(hipMemcpyAsync(it.data(), b.iters, sizeof(int) * S, hipMemcpyDeviceToHost, s));
-    RPA_HIP(hipMemcpyAsync(st.data(), b.status, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+int tally(const Chi0Buf& b, int S, int64_t nd, SolveTally& t, Chi0Host& h, int64_t sys0,
+          hipStream_t s) {
+    h.it.assign(S, 0);
+    h.st.assign(S, 0);
+    h.rf.assign(S, 0);
+    RPA_HIP(hipMemcpyAsync(h.it.data(), b.iters, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+    RPA_HIP(hipMemcpyAsync(h.st.data(), b.status, sizeof(int) * S, hipMemcpyDeviceToHost, s));
     if (b.mixed)
-        RPA_HIP(hipMemcpyAsync(rf.data(), b.refine, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipMemcpyAsync(h.rf.data(), b.refine, sizeof(int) * S, hipMemcpyDeviceToHost, s));
     RPA_HIP(hipStreamSynchronize(s));
     hipEvent_t e0, e1;
     RPA_CHECK(timer_events(&e0, &e1));
@@ -305,12 +360,13 @@ int tally(const Chi0Buf& b, int S, int64_t nd, SolveTally& t, hipStream_t s) {
     t.kernel_ms += ms;
     t.launches += 1;
     for (int i = 0; i < S; ++i) {
-        t.point_iters += double(it[i]) * double(nd);
-        t.iters_total += it[i];
-        t.iters_max = std::max(t.iters_max, it[i]);
-        t.refinements += rf[i];
-        t.unconv += (st[i] == 1);
-        t.breakdown += (st[i] == 2);
+        t.point_iters += double(h.it[i]) * double(nd);
+        t.iters_total += h.it[i];
+        t.iters_max = std::max(t.iters_max, h.it[i]);
+        t.refinements += h.rf[i];
+        t.unconv += (h.st[i] == 1);
+        t.breakdown += (h.st[i] == 2);
+        if (sys0 + i < int64_t(h.hint.size())) h.hint[sys0 + i] = h.it[i];
     }
     t.systems += S;
     return RPA_OK;
@@ -329,9 +385,35 @@ void add_stats(rpa_stats* st, const SolveTally& t) {
     st->cocg_point_iters += t.point_iters;
 }
 
-// Solve the Sternheimer systems of the trial vectors U[:, j0:j0+nv] at one frequency.
-int solve_chunk(const rpa_cell* cell, const Grid& g, double omega, const Opts& o,
-                const Chi0Buf& b, const double* U, int nv, bool x_complex, hipStream_t s) {
+// Dispatch order of the ns*nv systems of a chunk: the previous apply's iteration counts when
+// every system has one, else an estimate of the difficulty, 1/|eps_top - eps_n + 0.05 + i w|
+// (the shifted gap shrinks for orbitals near the top and for small frequencies); largest
+// first, ties by system index.
+void dispatch_order(const rpa_cell* cell, int nv, int64_t j0, Chi0Host& h) {
+    const int ns = cell->n_occ, S = ns * nv;
+    std::vector<double> key(S);
+    bool have = true;
+    for (int i = 0; i < S && have; ++i) have = h.hint[size_t(j0) * ns + i] >= 0;
+    for (int i = 0; i < S; ++i) {
+        if (have) {
+            key[i] = double(h.hint[size_t(j0) * ns + i]);
+        } else {
+            const int n = i % ns;
+            const double w = h.omega[j0 + i / ns];
+            key[i] = 1.0 / std::hypot(cell->eps[ns - 1] - cell->eps[n] + 0.05, w);
+        }
+    }
+    h.order.resize(S);
+    for (int i = 0; i < S; ++i) h.order[i] = i;
+    std::stable_sort(h.order.begin(), h.order.end(),
+                     [&](int a, int b) { return key[a] > key[b]; });
+}
+
+// Solve the Sternheimer systems of the trial vectors j0 .. j0+nv-1 (columns of U, which
+// points at column j0), each at its own frequency h.omega[j].
+int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Buf& b,
+                const double* U, int64_t j0, int nv, bool x_complex, Chi0Host& h,
+                hipStream_t s) {
     const int ns = cell->n_occ;
     const int64_t nd = g.nd();
     const double dV = g.h * g.h * g.h;
@@ -342,13 +424,21 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, double omega, const Opts& o
     else
         RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff,
                                         reinterpret_cast<double*>(b.r), nullptr, s));
+    h.om_chunk.assign(h.omega.begin() + j0, h.omega.begin() + j0 + nv);
+    dispatch_order(cell, nv, j0, h);
+    RPA_HIP(hipMemcpyAsync(b.omega_v, h.om_chunk.data(), sizeof(double) * nv,
+                           hipMemcpyHostToDevice, s));
+    RPA_HIP(hipMemcpyAsync(b.order, h.order.data(), sizeof(int) * ns * nv, hipMemcpyHostToDevice,
+                           s));
     CocgLaunch L{};
     L.g = g;
     L.nsys = ns * nv;
     L.ns = ns;
     L.vloc = cell->v_loc;
     L.eps = b.eps;
-    L.omega = omega;
+    L.omega = h.om_chunk[0];
+    L.omega_v = b.omega_v;
+    L.order = b.order;
     L.tol = o.cocg_tol;
     L.max_iter = o.cocg_max_iter;
     L.r = b.r;
@@ -371,17 +461,18 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, double omega, const Opts& o
     return RPA_OK;
 }
 
-int chi0_apply(const rpa_cell* cell, const Grid& g, double omega, int nvec, const double* in,
-               double* out, const Opts& o, const Chi0Buf& b, SolveTally& t, hipStream_t s) {
+// chi0 on nvec trial vectors, vector j at frequency h.omega[j].
+int chi0_apply(const rpa_cell* cell, const Grid& g, int nvec, const double* in, double* out,
+               const Opts& o, const Chi0Buf& b, Chi0Host& h, SolveTally& t, hipStream_t s) {
     const int ns = cell->n_occ;
     const int64_t nd = g.nd();
     RPA_HIP(hipMemcpyAsync(b.eps, cell->eps, sizeof(double) * ns, hipMemcpyHostToDevice, s));
     for (int j0 = 0; j0 < nvec; j0 += b.chunk) {
         const int nv = std::min(b.chunk, nvec - j0);
-        RPA_CHECK(solve_chunk(cell, g, omega, o, b, in + nd * j0, nv, false, s));
+        RPA_CHECK(solve_chunk(cell, g, o, b, in + nd * j0, j0, nv, false, h, s));
         RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
                             b.x_complex ? 2 : 1, out + nd * j0, s));
-        RPA_CHECK(tally(b, ns * nv, nd, t, s));
+        RPA_CHECK(tally(b, ns * nv, nd, t, h, int64_t(j0) * ns, s));
     }
     return RPA_OK;
 }
@@ -424,10 +515,12 @@ int subspace_iter(const rpa_cell* cell, const Grid& g, double omega, double weig
     if (!coulomb_ready) RPA_CHECK(coulomb_setup(g, b.cb, s));
     double Eprev = 0.0, E = 0.0;
     int k = 0;
+    Chi0Host h;
+    h.reset(cell->n_occ, nr, omega);
     for (;;) {
         ++k;
         RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, V, b.U, s));
-        RPA_CHECK(chi0_apply(cell, g, omega, nr, b.U, b.D, o, b.xb, t, s));
+        RPA_CHECK(chi0_apply(cell, g, nr, b.U, b.D, o, b.xb, h, t, s));
         RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, b.D, b.R, s));
         RPA_HIP(launch_gram(nd, nr, V, b.R, b.part, b.gsplit, b.C, s));
         RPA_HIP(launch_symmetrize(nr, b.C, s));
@@ -469,6 +562,113 @@ int subspace_iter(const rpa_cell* cell, const Grid& g, double omega, double weig
     }
     res.E = E;
     res.n_iter = k;
+    return RPA_OK;
+}
+
+
+// E_c of one cell with every frequency started from V0 and all frequencies still iterating
+// advanced together (one chi0 apply over their packed blocks per subspace iteration, each
+// trial vector at its own frequency).  Each frequency stops by the same test as the warm
+// driver.
+int energy_batched(const rpa_cell* cell, int nr, int nfreq, const double* omega,
+                   const double* weight, const double* V0, double* Vsave, double* Csave,
+                   const Opts& o, BatchBuf& b, SolveTally& t, rpa_stats* stats, double* ec,
+                   double* ec_freq, int32_t* iters, hipStream_t s) {
+    const Grid g = grid_of(cell);
+    const int64_t nd = g.nd();
+    const int ns = cell->n_occ;
+    const size_t blk = size_t(nd) * nr, sq = size_t(nr) * nr;
+    RPA_CHECK(coulomb_setup(g, b.cb, s));
+    // V0 -> orthonormal start (Cholesky-QR, as in the warm driver)
+    {
+        RPA_HIP(launch_gram(nd, nr, V0, V0, b.part, b.gsplit, b.M, s));
+        RPA_HIP(launch_chol_inv(nr, b.M, b.L, b.T, b.info, s));
+        int info = 0;
+        RPA_HIP(hipMemcpyAsync(&info, b.info, sizeof(int), hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipStreamSynchronize(s));
+        if (info != 0) return fail(RPA_ENOTPD, "Cholesky of V0^T V0 failed");
+        RPA_HIP(launch_gemm_tall_small(nd, nr, V0, b.T, b.Vstart, s));
+    }
+    for (int f = 0; f < nfreq; ++f) RPA_HIP(launch_copy(int64_t(blk), b.Vstart, b.Vall + f * blk, s));
+    std::vector<int> active(nfreq), k(nfreq, 0);
+    for (int f = 0; f < nfreq; ++f) active[f] = f;
+    std::vector<double> E(nfreq, 0.0), Eprev(nfreq, 0.0);
+    std::vector<std::vector<int>> hintf(nfreq, std::vector<int>(size_t(ns) * nr, -1));
+    std::vector<double> escal(8 * size_t(nfreq));
+    std::vector<int> info(8 * size_t(nfreq));
+    Chi0Host h;
+    while (!active.empty()) {
+        const int na = int(active.size()), ncol = na * nr;
+        h.omega.resize(ncol);
+        h.hint.resize(size_t(ns) * ncol);
+        for (int a = 0; a < na; ++a) {
+            const int f = active[a];
+            RPA_HIP(launch_copy(int64_t(blk), b.Vall + f * blk, b.P + a * blk, s));
+            for (int j = 0; j < nr; ++j) h.omega[size_t(a) * nr + j] = omega[f];
+            std::copy(hintf[f].begin(), hintf[f].end(), h.hint.begin() + size_t(a) * ns * nr);
+        }
+        RPA_CHECK(coulomb_apply(g, b.cb, 1, ncol, b.P, b.U, s));
+        RPA_CHECK(chi0_apply(cell, g, ncol, b.U, b.D, o, b.xb, h, t, s));
+        RPA_CHECK(coulomb_apply(g, b.cb, 1, ncol, b.D, b.R, s));
+        for (int a = 0; a < na; ++a) {
+            const int f = active[a];
+            std::copy(h.hint.begin() + size_t(a) * ns * nr, h.hint.begin() + size_t(a + 1) * ns * nr,
+                      hintf[f].begin());
+            double* C = b.C + f * sq;
+            RPA_HIP(launch_gram(nd, nr, b.P + a * blk, b.R + a * blk, b.part, b.gsplit, C, s));
+            RPA_HIP(launch_symmetrize(nr, C, s));
+            RPA_HIP(launch_energy_logdet(nr, C, weight[f] / (2.0 * M_PI), b.ework, b.escal + 8 * f,
+                                         b.info + 8 * f, s));
+            RPA_HIP(launch_gram(nd, nr, b.R + a * blk, b.R + a * blk, b.part, b.gsplit, b.M + f * sq, s));
+            RPA_HIP(launch_chol_inv(nr, b.M + f * sq, b.L + f * sq, b.T + f * sq, b.info + 8 * f + 1, s));
+        }
+        RPA_HIP(hipMemcpyAsync(escal.data(), b.escal, sizeof(double) * 8 * nfreq,
+                               hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipMemcpyAsync(info.data(), b.info, sizeof(int) * 8 * nfreq, hipMemcpyDeviceToHost, s));
+        RPA_HIP(hipStreamSynchronize(s));
+        if (stats) {
+            stats->chi0_applies += na;
+            stats->subspace_iters_total += na;
+        }
+        std::vector<int> next;
+        for (int a = 0; a < na; ++a) {
+            const int f = active[a];
+            const double Ef = escal[8 * f];
+            if (info[8 * f] != 0 || !std::isfinite(Ef)) {
+                if (t.breakdown)
+                    return fail(RPA_EBREAKDOWN, "COCG breakdown in " + std::to_string(t.breakdown) +
+                                                    " system(s); I - C not positive definite");
+                if (t.unconv)
+                    return fail(RPA_ENOTPD, std::to_string(t.unconv) + " COCG system(s) hit "
+                                            "cocg_max_iter; I - C not positive definite");
+                return fail(info[8 * f] != 0 ? RPA_ENOTPD : RPA_EINVAL,
+                            info[8 * f] != 0 ? "I - C is not positive definite"
+                                             : "non-finite subspace energy");
+            }
+            if (info[8 * f + 1] != 0)
+                return fail(RPA_ENOTPD, "Cholesky of R^T R failed at column " +
+                                            std::to_string(info[8 * f + 1]));
+            if (Vsave) RPA_HIP(launch_copy(int64_t(blk), b.P + a * blk, Vsave + f * blk, s));
+            if (Csave) RPA_HIP(launch_copy(int64_t(sq), b.C + f * sq, Csave + f * sq, s));
+            RPA_HIP(launch_gemm_tall_small(nd, nr, b.R + a * blk, b.T + f * sq, b.Vall + f * blk, s));
+            E[f] = Ef;
+            k[f] += 1;
+            bool stop;
+            if (o.ec_tol <= 0.0) stop = (k[f] >= o.subspace_iters);
+            else stop = (k[f] >= o.subspace_iters) ||
+                        (k[f] >= 2 && std::fabs(Ef - Eprev[f]) <= o.ec_tol * std::fabs(Ef));
+            Eprev[f] = Ef;
+            if (!stop) next.push_back(f);
+        }
+        active.swap(next);
+    }
+    double total = 0.0;
+    for (int f = 0; f < nfreq; ++f) {
+        total += E[f];
+        if (ec_freq) ec_freq[f] = E[f];
+        if (iters) iters[f] = k[f];
+    }
+    *ec = total;
     return RPA_OK;
 }
 
@@ -532,7 +732,15 @@ int rpa_workspace_size(int32_t op, int32_t ncell, const rpa_cell* cells, const i
             case RPA_OP_COULOMB: { CoulombBuf b; carve_coulomb(cv, g, nvec[c], b); break; }
             case RPA_OP_CHI0: { Chi0Buf b; carve_chi0(cv, g, ns, nvec[c], o, false, false, b); break; }
             case RPA_OP_SUBSPACE: { SubBuf b; carve_sub(cv, g, ns, nvec[c], o, b); break; }
-            case RPA_OP_ENERGY: { EnergyBuf b; carve_energy(cv, g, ns, nvec[c], o, b); break; }
+            case RPA_OP_ENERGY: {
+                if (o.freq_mode == RPA_INDEPENDENT) {
+                    if (nfreq < 1) return fail(RPA_EINVAL, "nfreq must be >= 1");
+                    BatchBuf b; carve_batch(cv, g, ns, nvec[c], nfreq, o, b);
+                } else {
+                    EnergyBuf b; carve_energy(cv, g, ns, nvec[c], o, b);
+                }
+                break;
+            }
             case RPA_OP_BACKWARD: {
                 if (nfreq < 1) return fail(RPA_EINVAL, "nfreq must be >= 1");
                 BackBuf b; carve_back(cv, g, ns, nvec[c], o, b); break;
@@ -585,7 +793,9 @@ int rpa_apply_chi0(const rpa_cell* cell, double omega, int32_t nvec, const doubl
     carve_chi0(cv, g, cell->n_occ, nvec, o, false, false, b);
     hipStream_t s = static_cast<hipStream_t>(stream);
     SolveTally t;
-    RPA_CHECK(chi0_apply(cell, g, omega, nvec, in, out, o, b, t, s));
+    Chi0Host h;
+    h.reset(cell->n_occ, nvec, omega);
+    RPA_CHECK(chi0_apply(cell, g, nvec, in, out, o, b, h, t, s));
     add_stats(stats, t);
     if (stats) stats->chi0_applies += 1;
     return solve_status(t);
@@ -645,13 +855,38 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
             return fail(RPA_EINVAL, "nr must be in [1, min(4096, N_d)]");
         if (!V0[c]) return fail(RPA_EINVAL, "V0 pointer is NULL");
         Carver dry;
-        EnergyBuf b;
-        carve_energy(dry, g, cells[c].n_occ, nr[c], o, b);
+        if (o.freq_mode == RPA_INDEPENDENT) {
+            BatchBuf b;
+            carve_batch(dry, g, cells[c].n_occ, nr[c], nfreq, o, b);
+        } else {
+            EnergyBuf b;
+            carve_energy(dry, g, cells[c].n_occ, nr[c], o, b);
+        }
         need = std::max(need, dry.used);
     }
     RPA_CHECK(check_ws(ws, ws_bytes, need));
     hipStream_t s = static_cast<hipStream_t>(stream);
     SolveTally t;
+    if (o.freq_mode == RPA_INDEPENDENT) {
+        for (int c = 0; c < ncell; ++c) {
+            const rpa_cell* cell = &cells[c];
+            const Grid g = grid_of(cell);
+            Carver cv{static_cast<char*>(ws), 0};
+            BatchBuf b;
+            carve_batch(cv, g, cell->n_occ, nr[c], nfreq, o, b);
+            int rc = energy_batched(cell, nr[c], nfreq, omega, weight, V0[c],
+                                    (Vsave && Vsave[c]) ? Vsave[c] : nullptr,
+                                    (Csave && Csave[c]) ? Csave[c] : nullptr, o, b, t, stats,
+                                    &ec_out[c], ec_freq_out ? ec_freq_out + size_t(c) * nfreq : nullptr,
+                                    iters_out ? iters_out + size_t(c) * nfreq : nullptr, s);
+            if (rc < 0) {
+                add_stats(stats, t);
+                return rc;
+            }
+        }
+        add_stats(stats, t);
+        return solve_status(t);
+    }
     for (int c = 0; c < ncell; ++c) {
         const rpa_cell* cell = &cells[c];
         const Grid g = grid_of(cell);
@@ -665,8 +900,6 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
         RPA_HIP(launch_copy(nd * m_r, b.Vstart, b.Vcur, s));
         double total = 0.0;
         for (int m = 0; m < nfreq; ++m) {
-            if (o.freq_mode == RPA_INDEPENDENT && m > 0)
-                RPA_HIP(launch_copy(nd * m_r, b.Vstart, b.Vcur, s));
             double* vs = (Vsave && Vsave[c]) ? Vsave[c] + size_t(m) * nd * m_r : nullptr;
             double* csv = (Csave && Csave[c]) ? Csave[c] + size_t(m) * m_r * m_r : nullptr;
             SubResult res;
@@ -718,7 +951,9 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
     RPA_HIP(hipMemcpyAsync(b.xb.eps, cell->eps, sizeof(double) * ns, hipMemcpyHostToDevice, s));
     RPA_HIP(launch_fill(nd, 0.0, grad_vloc, s));
     std::vector<double> mu(nr), ck(nr);
+    Chi0Host h;
     for (int m = 0; m < nfreq; ++m) {
+        h.reset(ns, nr, omega[m]);
         const double* Vm = Vsave + size_t(m) * nd * nr;
         const double* Cm = Csave + size_t(m) * nr * nr;
         RPA_HIP(launch_syevj(nr, Cm, b.eigwork, b.mu, b.Y, s));
@@ -730,10 +965,10 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
         RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, b.W, b.U, s));
         for (int j0 = 0; j0 < nr; j0 += b.xb.chunk) {
             const int nv = std::min(b.xb.chunk, nr - j0);
-            RPA_CHECK(solve_chunk(cell, g, omega[m], o, b.xb, b.U + nd * j0, nv, b.xb.x_complex, s));
+            RPA_CHECK(solve_chunk(cell, g, o, b.xb, b.U + nd * j0, j0, nv, b.xb.x_complex, h, s));
             RPA_HIP(launch_grad_accum_d(nd, ns, nv, cell->psi, b.xb.eps, omega[m], b.xb.coeff,
                                         b.xb.dbuf, b.coefk + j0, b.xb.x, false, grad_vloc, s));
-            RPA_CHECK(tally(b.xb, ns * nv, nd, t, s));
+            RPA_CHECK(tally(b.xb, ns * nv, nd, t, h, int64_t(j0) * ns, s));
         }
         if (stats) stats->chi0_applies += 1;
     }

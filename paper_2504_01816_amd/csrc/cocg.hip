@@ -155,6 +155,8 @@ hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     a.eps = L.eps;
     a.ns = L.ns;
     a.omega = L.omega;
+    a.omega_v = L.omega_v;
+    a.order = L.order;
     a.tol2 = L.tol * L.tol;
     a.refine2 = L.refine_tol * L.refine_tol;
     a.max_iter = L.max_iter;

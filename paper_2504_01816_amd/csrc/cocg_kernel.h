@@ -45,7 +45,9 @@ struct Args {
     const double* vloc;
     const double* eps;
     int ns;
-    double omega;
+    double omega;          // shift of every system when omega_v is null
+    const double* omega_v; // per trial vector j (system s = n + ns j): its frequency, or null
+    const int* order;      // workgroup b solves system order[b] (a permutation), or null
     double tol2;
     double refine2;        // mixed: refine_tol^2
     int max_iter;
@@ -431,18 +433,22 @@ __device__ __forceinline__ void fold_xlo(const Args& a, const int (&col)[C], con
 template <typename T, typename XS, int C, int Z, int BSMAX, int OCC = 0>
 __global__ __attribute__((amdgpu_flat_work_group_size(64, BSMAX),
                           amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
-void cocg_wg(Args a) {
+void cocg_wg(Args a_in) {
     using T2 = typename Cplx<T>::type;
     constexpr bool MIXED = std::is_same<T, float>::value;
-    // Hardest systems first: orbitals closest to the gap (largest n) have the smallest shifted
-    // gap and need the most iterations, so they are dispatched before the easier ones, which
-    // then fill the CUs behind them instead of leaving a long single-system tail.  System
-    // s = n + ns*j; workgroup b takes n = ns-1 - b / nvec, j = b % nvec.
-    const int nvec_l = int(gridDim.x) / a.ns;
+    // Dispatch order: the host passes a permutation that starts the systems expected to need
+    // the most iterations first (longest-first list scheduling: the easy ones then fill the
+    // CUs behind them instead of leaving a long single-system tail).  Without one, orbitals
+    // closest to the gap (largest n, smallest shifted gap) go first: system s = n + ns*j,
+    // workgroup b takes n = ns-1 - b / nvec, j = b % nvec.
+    const int nvec_l = int(gridDim.x) / a_in.ns;
     const int bid = blockIdx.x;
-    const int sys = (nvec_l > 0 && int(gridDim.x) % a.ns == 0)
-                        ? (a.ns - 1 - bid / nvec_l) + a.ns * (bid % nvec_l)
+    const int sys = a_in.order ? a_in.order[bid]
+                  : (nvec_l > 0 && int(gridDim.x) % a_in.ns == 0)
+                        ? (a_in.ns - 1 - bid / nvec_l) + a_in.ns * (bid % nvec_l)
                         : bid;
+    Args a = a_in;
+    if (a_in.omega_v) a.omega = a_in.omega_v[sys / a_in.ns];
     const int tid = threadIdx.x, BS = blockDim.x;
     const int n0 = a.n0, P = a.P;
     const int64_t off = int64_t(sys) * a.nd;

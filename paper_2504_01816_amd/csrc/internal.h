@@ -89,7 +89,9 @@ struct CocgLaunch {
     int ns;                // orbitals (system s uses eps[s % ns])
     const double* vloc;    // N_d
     const double* eps;     // device, ns
-    double omega;
+    double omega;          // shift of every system unless omega_v is set
+    const double* omega_v; // device, nsys / ns: frequency of trial vector j, or null
+    const int* order;      // device, nsys: dispatch order (a permutation of 0..nsys-1), or null
     double tol;
     int max_iter;
     void* r;               // nsys x N_d complex (T2)

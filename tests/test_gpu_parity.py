@@ -227,3 +227,64 @@ def test_mixed_backward_matches_fp64():
                                           dict(o64, precision=MIXED))
     assert rc == 0 and st["refinements"] > 0
     assert rel(gmx.cpu().numpy(), g64.cpu().numpy()) < 1e-8
+
+
+# ---------------------------------------------------------------------------- batched frequencies
+INDEPENDENT = 1
+
+
+@pytest.fixture(scope="module")
+def small3():
+    c = synth.small_cell(n=12, h=0.5, n_wells=2, n_occ=3, seed=11)
+    om, W = synth.frequency_rule(3)
+    V0 = np.random.default_rng(8).standard_normal((6, c.nd))
+    ref = oenergy.rpa_energy(c.vloc, c.psi.T, c.eps, c.shape, c.h, V0.T, om, W, 1e-11, 5000, 3,
+                             mode="independent")
+    return c, om, W, V0, ref
+
+
+@pytest.mark.parametrize("precision", [0, MIXED])
+def test_independent_frequencies_batched_match_oracle(small3, precision):
+    # every frequency starts from V0; the GPU advances all three in one chi0 launch per
+    # subspace iteration (per-system shifts), the oracle one frequency after the other
+    c, om, W, V0, ref = small3
+    say("batched independent frequencies, precision", precision)
+    dc = api.device_cell(c, DEV)
+    res = api.rpa_energy(dc, 6, om, W, [torch.tensor(V0, device=DEV)],
+                         dict(cocg_tol=1e-11, subspace_iters=3, ec_tol=0.0,
+                              freq_mode=INDEPENDENT, precision=precision), save=True)
+    assert res["status"] == 0
+    assert list(res["iters"][0]) == [3, 3, 3]
+    np.testing.assert_allclose(res["E_freq"][0], ref["E_freq"], rtol=1e-9)
+    assert abs(res["E_c"][0] - ref["E_c"]) <= 1e-9 * abs(ref["E_c"])
+    # each saved (V_m, C_m) is the pair behind E_m
+    for m in range(3):
+        C = res["Csave"][0][m].cpu().numpy()
+        mu = np.linalg.eigvalsh(0.5 * (C + C.T))
+        # log-det route vs eigenvalue route: g(mu) ~ mu^2/2 loses ~eps/|mu| relative
+        assert abs(W[m] * np.sum(osub.g(mu)) / (2 * np.pi) - res["E_freq"][0][m]) \
+            <= 1e-10 * abs(res["E_freq"][0][m])
+    # the backward consumes the batched saves like the warm ones
+    grad, rc, _ = api.rpa_energy_backward(dc, om, W, res["Vsave"][0], res["Csave"][0], 1.0,
+                                          dict(cocg_tol=1e-11))
+    Vs = [res["Vsave"][0][m].cpu().numpy().T for m in range(3)]
+    Cs = [res["Csave"][0][m].cpu().numpy() for m in range(3)]
+    gref = ograd.energy_backward(c.vloc, c.psi.T, c.eps, c.shape, c.h, om, W, Vs, Cs, 1e-12, 5000)
+    assert rc == 0 and rel(grad.cpu().numpy(), gref) < 1e-8
+
+
+def test_independent_batched_stops_each_frequency_on_its_own(small3):
+    # with an energy tolerance the frequencies stop at different counts; the result for each
+    # equals a single-frequency run of the same length
+    c, om, W, V0, _ = small3
+    say("batched independent frequencies, per-frequency stopping")
+    dc = api.device_cell(c, DEV)
+    opts = dict(cocg_tol=1e-11, subspace_iters=12, ec_tol=1e-7, freq_mode=INDEPENDENT)
+    res = api.rpa_energy(dc, 6, om, W, [torch.tensor(V0, device=DEV)], opts)
+    its = res["iters"][0]
+    assert res["status"] == 0 and its.min() >= 2
+    for m in range(3):
+        one = api.rpa_energy(dc, 6, [om[m]], [W[m]], [torch.tensor(V0, device=DEV)],
+                             dict(opts, subspace_iters=int(its[m]), ec_tol=0.0))
+        assert abs(one["E_c"][0] - res["E_freq"][0][m]) <= 1e-9 * abs(one["E_c"][0])
+
