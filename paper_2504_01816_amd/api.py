@@ -212,3 +212,30 @@ def rpa_energy_backward(cell, omegas, weights, Vsave, Csave, grad_ec=1.0, opts=N
         ctypes.byref(st), ws, nbytes, _stream()), "rpa_energy_backward")
     del keep
     return grad, rc, st.as_dict()
+
+
+class RPAEnergy(torch.autograd.Function):
+    """E_c as a differentiable function of V_loc (orbitals, eigenvalues and the subspaces
+    found by the forward held fixed): forward = rpa_energy (saving V_m, C_m), backward =
+    rpa_energy_backward with the incoming gradient as grad_ec.
+
+        E = RPAEnergy.apply(vloc, cell, nr, omegas, weights, V0, opts)
+
+    vloc: (N_d,) float64 device tensor (requires_grad as needed); cell: a DeviceCell whose
+    psi, eps, shape and h are used (its vloc is replaced by the argument); V0: (nr, N_d).
+    Returns a 0-d float64 tensor on the device of vloc."""
+
+    @staticmethod
+    def forward(ctx, vloc, cell, nr, omegas, weights, V0, opts=None):
+        dc = DeviceCell(cell.shape, cell.h, vloc.detach().contiguous(), cell.psi, cell.eps)
+        res = rpa_energy(dc, nr, omegas, weights, V0, opts, save=True)
+        ctx.dc, ctx.omegas, ctx.weights, ctx.opts = dc, list(omegas), list(weights), opts
+        ctx.save_for_backward(res["Vsave"][0], res["Csave"][0])
+        return torch.tensor(float(res["E_c"][0]), dtype=torch.float64, device=vloc.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        Vs, Cs = ctx.saved_tensors
+        g, _, _ = rpa_energy_backward(ctx.dc, ctx.omegas, ctx.weights, Vs, Cs,
+                                      float(grad_out), ctx.opts)
+        return g, None, None, None, None, None, None

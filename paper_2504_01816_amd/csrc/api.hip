@@ -147,7 +147,7 @@ struct Chi0Buf {
     double* part;
     void *r, *pa, *pb, *x;
     void* xlo;      // mixed only
-    double* b;      // mixed only
+    double* rhi;    // mixed only: complex float64 residual
     int *iters, *status, *refine;
     double* omega_v;  // per trial vector of a chunk: its frequency
     int* order;       // per system of a chunk: dispatch order
@@ -200,7 +200,7 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     b.pb = cv.take<char>(size_t(S) * nd * cplx);
     b.x = cv.take<char>(size_t(S) * nd * (b.x_complex ? 16 : 8));
     b.xlo = b.mixed ? cv.take<char>(size_t(S) * nd * 8) : nullptr;
-    b.b = b.mixed ? cv.take<double>(size_t(S) * nd) : nullptr;
+    b.rhi = b.mixed ? cv.take<double>(2 * size_t(S) * nd) : nullptr;
     b.iters = cv.take<int>(S);
     b.status = cv.take<int>(S);
     b.refine = cv.take<int>(S);
@@ -420,7 +420,7 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
     RPA_HIP(launch_proj_coeff(nd, ns, nv, dV, cell->psi, U, b.part, b.nsplit, b.coeff, s));
     if (b.mixed)
         RPA_HIP(launch_proj_rhs<float>(nd, ns, nv, cell->psi, U, b.coeff,
-                                       reinterpret_cast<float*>(b.r), b.b, s));
+                                       reinterpret_cast<float*>(b.r), b.rhi, s));
     else
         RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff,
                                         reinterpret_cast<double*>(b.r), nullptr, s));
@@ -450,7 +450,7 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
     L.status = b.status;
     L.fp32 = b.mixed;
     L.xlo = b.xlo;
-    L.b = b.b;
+    L.rhi = b.rhi;
     L.refinements = b.refine;
     L.refine_tol = o.refine_tol;
     hipEvent_t e0, e1;

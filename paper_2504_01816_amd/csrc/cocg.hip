@@ -167,7 +167,7 @@ hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     a.pb = L.pb;
     a.x = L.x;
     a.xlo = L.xlo;
-    a.b = L.b;
+    a.rhi = L.rhi;
     a.iters = L.iters;
     a.status = L.status;
     a.refinements = L.refinements;

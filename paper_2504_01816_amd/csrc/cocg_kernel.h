@@ -17,11 +17,12 @@
 //    only orders LDS (global loads and stores stay in flight): every global address is
 //    read and written by one thread only, so LDS is the sole cross-thread channel.
 //  * Mixed precision (T = float): r, p and the partial solution x_lo are complex64; the
-//    solution x_hi and the right-hand side b are float64.  When the complex64 residual has
-//    dropped by refine_tol since the last refinement (or reaches the tolerance), the
-//    partial solution is folded into x_hi and r is replaced by the true residual b - A x_hi
-//    computed in float64 (reliable update); p and the Krylov recurrence continue.  The
-//    tolerance test uses that float64 residual.
+//    solution x_hi and the residual r_hi are complex float64.  When the complex64 residual
+//    has dropped by refine_tol since the last update (or reaches the tolerance), a reliable
+//    update (group-wise residual replacement) runs: x_hi += x_lo and r_hi -= A x_lo, with
+//    A x_lo evaluated in float64 from the exact complex64 values, so r_hi = b - A x_hi holds
+//    to float64 rounding; then r <- complex64(r_hi).  p and the Krylov recurrence continue.
+//    The tolerance test uses |r_hi|.
 //  * Reductions accumulate in float64 and are fixed-order: results are bitwise
 //    reproducible run to run.
 // Layout: state arrays are system-major, nsys x N_d, complex interleaved (re, im).
@@ -58,7 +59,7 @@ struct Args {
     void* pb;              // complex T
     void* x;               // FP64 path: real or complex double; mixed: complex double x_hi
     void* xlo;             // mixed: complex float
-    const double* b;       // mixed: real double right-hand side
+    double* rhi;           // mixed: complex double residual (starts at the right-hand side)
     int* iters;
     int* status;
     int* refinements;      // mixed: per system
@@ -154,8 +155,9 @@ __device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int n1, int c
 // reads are consumed before the next k's are issued (the empty asm ties the accumulators),
 // which bounds the registers held by reads in flight.
 template <typename R, typename Q2, int NQ, int C>
-__device__ __forceinline__ Q2 stencil(const Args& a, const Q2* __restrict__ L, const Q2 (&Q)[NQ][C],
-                                      int zc, int i, int cx, int cy, R diag, R om) {
+__device__ __forceinline__ typename Cplx<R>::type stencil(const Args& a, const Q2* __restrict__ L,
+                                                          const Q2 (&Q)[NQ][C], int zc, int i,
+                                                          int cx, int cy, R diag, R om) {
     const int RS = a.rs;
     const Q2* Lc = L + lds_center(RS, cx, cy);
     R ax = 0, ay = 0;
@@ -164,12 +166,12 @@ __device__ __forceinline__ Q2 stencil(const Args& a, const Q2* __restrict__ L, c
         const Q2 a1 = Lc[k], a2 = Lc[-k];
         const Q2 b1 = Lc[k * RS], b2 = Lc[-k * RS];
         const Q2 c1 = Q[zc + k][i], c2 = Q[zc - k][i];
-        ax += R(a.cw[k]) * (((a1.x + a2.x) + (b1.x + b2.x)) + (c1.x + c2.x));
-        ay += R(a.cw[k]) * (((a1.y + a2.y) + (b1.y + b2.y)) + (c1.y + c2.y));
+        ax += R(a.cw[k]) * (((R(a1.x) + R(a2.x)) + (R(b1.x) + R(b2.x))) + (R(c1.x) + R(c2.x)));
+        ay += R(a.cw[k]) * (((R(a1.y) + R(a2.y)) + (R(b1.y) + R(b2.y))) + (R(c1.y) + R(c2.y)));
         if (k % RPA_STENCIL_GROUP == 0) asm volatile("" : "+v"(ax), "+v"(ay) :: "memory");
     }
     const Q2 c = Q[zc][i];
-    return Q2{ax + diag * c.x + om * c.y, ay + diag * c.y - om * c.x};
+    return typename Cplx<R>::type{ax + diag * R(c.x) + om * R(c.y), ay + diag * R(c.y) - om * R(c.x)};
 }
 
 // Generic z-march: lead.load(z, i, first) fetches what the queue entry of plane z needs
@@ -273,9 +275,12 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
                 if (!cl.valid[i]) continue;
                 const unsigned idx = unsigned((zo + zz) * P + cl.col[i]);
                 const R diag = R(a.cw[0] + ld(a.vloc, idx) - eps_n);
-                const Q2 q = stencil<R, Q2, NQ, C>(a, L + zz * PL, Q, 6 + zz, i, cl.cx[i], cl.cy[i],
-                                                   diag, om);
+                const auto q = stencil<R, Q2, NQ, C>(a, L + zz * PL, Q, 6 + zz, i, cl.cx[i],
+                                                     cl.cy[i], diag, om);
                 cent.finish(CC[zz][i], zo + zz, i, Q[6 + zz][i], q);
+                // one column at a time: keeps the next column's LDS reads (and registers)
+                // behind this column's stores
+                if (C > 1) asm volatile("" ::: "memory");
             }
         }
         if (a.nbuf == 1) lds_barrier();      // single buffer: reads done before the next write
@@ -370,39 +375,37 @@ struct CentUpdate {
 };
 
 // ---------------------------------------------------------------- reliable update (mixed)
-// One z-march in float64 over x_hi: the lead folds the pending complex64 partial solution
-// into x_hi (x_hi + x_lo) for planes whose centre step has not run yet, and reads the stored
-// x_hi for planes already written back (the periodic wrap at the end of the sweep); the
-// centre step stores the folded x_hi and the true residual r = b - A x_hi (complex64), and
-// accumulates r^T r and |r|^2.  Every address is read and written by its own thread only.
-struct LeadFold {
-    struct Buf { double2 h; float2 l; bool fold; };
-    const double2* xhi; const float2* xlo; int P; const int* col; bool xhi_zero;
-    __device__ Buf load(int z, int i, bool first) const {
+// One z-march over x_lo with a complex64 queue; the stencil promotes every value to float64.
+// The centre step adds x_lo to x_hi, subtracts A x_lo from r_hi, stores both and
+// r = complex64(r_hi), and accumulates r^T r (of the stored complex64 r) and |r_hi|^2.
+// Every address is read and written by its own thread only.
+struct LeadXlo {
+    using Buf = float2;
+    const float2* xlo; int P; const int* col;
+    __device__ Buf load(int z, int i, bool) const { return ld(xlo, unsigned(z * P + col[i])); }
+    __device__ float2 make(const Buf& b) const { return b; }
+};
+struct CentRhi {
+    struct Buf { double2 rh, xh; };
+    double2* rhi; double2* xhi; float2* r; int P; const int* col; bool xhi_zero;
+    double acc[3];   // rho re/im, |r_hi|^2
+    __device__ Buf load(int z, int i) const {
         const unsigned idx = unsigned(z * P + col[i]);
         Buf b;
-        b.fold = first;
-        b.h = (xhi_zero && first) ? double2{0.0, 0.0} : ld(xhi, idx);
-        b.l = first ? ld(xlo, idx) : float2{0.0f, 0.0f};
+        b.rh = ld(rhi, idx);
+        b.xh = xhi_zero ? double2{0.0, 0.0} : ld(xhi, idx);
         return b;
     }
-    __device__ double2 make(const Buf& b) const {
-        return double2{b.h.x + double(b.l.x), b.h.y + double(b.l.y)};
-    }
-};
-struct CentResid {
-    using Buf = double;
-    double2* xhi; const double* b; float2* r; int P; const int* col;
-    double acc[3];   // rho re/im, |r|^2
-    __device__ Buf load(int z, int i) const { return ld(b, unsigned(z * P + col[i])); }
-    __device__ void finish(const Buf& bv, int z, int i, double2 c, double2 q) {
+    __device__ void finish(const Buf& bf, int z, int i, float2 c, double2 q) {
         const unsigned idx = unsigned(z * P + col[i]);
-        st(xhi, idx, c);
-        const float2 rv = float2{float(bv - q.x), float(-q.y)};
+        const double2 rh{bf.rh.x - q.x, bf.rh.y - q.y};
+        st(rhi, idx, rh);
+        st(xhi, idx, double2{bf.xh.x + double(c.x), bf.xh.y + double(c.y)});
+        const float2 rv{float(rh.x), float(rh.y)};
         st(r, idx, rv);
         acc[0] += double(rv.x) * rv.x - double(rv.y) * rv.y;
         acc[1] += 2.0 * double(rv.x) * rv.y;
-        acc[2] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+        acc[2] += rh.x * rh.x + rh.y * rh.y;
     }
 };
 
@@ -473,6 +476,7 @@ void cocg_wg(Args a_in) {
     double rho_re = 0, rho_im = 0, bb = 0, beta_re = 0, beta_im = 0, rr_ref = 0;
     int it = 0, st = 0, nref = 0;
     bool xlo_zero = true, xhi_zero = true, done = false;
+    bool cold = false;     // the queue was dropped (reliable update): sweep 1 reloads it
     // Queue of the swept vector, carried from sweep to sweep: after sweep 1 it holds planes
     // -6 .. 5 of the new p, which is what sweep 2 starts from; after sweep 2 it still holds
     // those planes of p, and the next sweep 1 starts from r' + beta' p on them.
@@ -481,7 +485,7 @@ void cocg_wg(Args a_in) {
     while (!done) {
         const bool first = (it == 0);
         // ---------------------------------------------------------- sweep 1
-        if (!first) {
+        if (!first && !cold) {
             // warm start of sweep 1 from the queue: p_new = r + beta p on planes -6 .. 5,
             // four planes at a time
             const T br = T(beta_re), bi = T(beta_im);
@@ -508,7 +512,8 @@ void cocg_wg(Args a_in) {
         }
         LeadPnew<T2, C> l1{r, pa, P, cl.col, first, beta_re, beta_im};
         CentSigma<T2, C> c1{pb, P, cl.col, first, {0, 0, 0, 0, 0, 0, 0}};
-        march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q, !first);
+        march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q, !first && !cold);
+        cold = false;
         wg_reduce<7>(c1.acc, red);
         if (first) {
             rho_re = c1.acc[4];
@@ -558,13 +563,20 @@ void cocg_wg(Args a_in) {
             if constexpr (MIXED) {
                 // reliable update when the complex64 residual fell by refine_tol or hit tol
                 if (acc2[2] <= a.tol2 * bb || acc2[2] <= a.refine2 * rr_ref) {
-                    double2 Qd[12 + 1][C];
-                    LeadFold lf{reinterpret_cast<const double2*>(a.x) + off,
-                                reinterpret_cast<const float2*>(a.xlo) + off, P, cl.col, xhi_zero};
-                    CentResid cr{reinterpret_cast<double2*>(a.x) + off, a.b + off,
-                                 reinterpret_cast<float2*>(r), P, cl.col, {0, 0, 0}};
-                    march<double, double2, C, 1>(a, cl, reinterpret_cast<double2*>(planes), eps_n,
-                                                 lf, cr, Qd, false);
+                    // drop the carried queue so that its registers are free for this sweep;
+                    // the next sweep 1 reloads its first planes from memory
+#pragma unroll
+                    for (int q = 0; q < 12 + Z; ++q)
+#pragma unroll
+                        for (int i = 0; i < C; ++i) Q[q][i] = T2{0, 0};
+                    cold = true;
+                    float2 Qx[12 + 1][C];
+                    LeadXlo lx{reinterpret_cast<const float2*>(a.xlo) + off, P, cl.col};
+                    CentRhi cr{reinterpret_cast<double2*>(a.rhi) + off,
+                               reinterpret_cast<double2*>(a.x) + off, reinterpret_cast<float2*>(r),
+                               P, cl.col, xhi_zero, {0, 0, 0}};
+                    march<double, float2, C, 1>(a, cl, reinterpret_cast<float2*>(planes), eps_n,
+                                                lx, cr, Qx, false);
                     wg_reduce<3>(cr.acc, red);
                     xhi_zero = false;
                     xlo_zero = true;

@@ -152,13 +152,16 @@ struct PsiKN {  // B(l, r) = psi[r + nd l]
 };
 template <typename T>
 struct StoreRhs {  // r0[s][r] = -(psi_n u_j - acc), complex with zero imaginary part
-    const double* psi; const double* U; int64_t nd; int ns; T* r0; double* b64;
+    const double* psi; const double* U; int64_t nd; int ns; T* r0; double* r64;
     __device__ void operator()(int s, int r, int, double acc) const {
         const int n = s % ns, j = s / ns;
         const double b = psi[r + nd * n] * U[r + nd * j] - acc;
         r0[2 * (int64_t(s) * nd + r)] = T(-b);
         r0[2 * (int64_t(s) * nd + r) + 1] = T(0);
-        if (b64) b64[int64_t(s) * nd + r] = -b;
+        if (r64) {   // the same right-hand side as complex float64
+            r64[2 * (int64_t(s) * nd + r)] = -b;
+            r64[2 * (int64_t(s) * nd + r) + 1] = 0.0;
+        }
     }
 };
 
@@ -309,10 +312,10 @@ hipError_t launch_proj_coeff(int64_t nd, int ns, int nvec, double dV, const doub
 
 template <typename T>
 hipError_t launch_proj_rhs(int64_t nd, int ns, int nvec, const double* psi, const double* U,
-                           const double* coeff, T* r0, double* b64, hipStream_t s) {
+                           const double* coeff, T* r0, double* r64, hipStream_t s) {
     const int S = ns * nvec;
     return run_gemm(S, int(nd), ns, 1, 0, CoeffT{coeff, ns}, PsiKN{psi, nd},
-                    StoreRhs<T>{psi, U, nd, ns, r0, b64}, s);
+                    StoreRhs<T>{psi, U, nd, ns, r0, r64}, s);
 }
 template hipError_t launch_proj_rhs<double>(int64_t, int, int, const double*, const double*,
                                             const double*, double*, double*, hipStream_t);

@@ -76,11 +76,11 @@ hipError_t launch_proj_coeff(int64_t nd, int ns, int nvec, double dV, const doub
                              const double* U, double* part, int nsplit, double* coeff,
                              hipStream_t s);
 // r0[s][r] = -(psi[r,n] u[r,j] - sum_l psi[r,l] coeff[l,s]) written as complex (T = float or
-// double) with zero imaginary part; if b64 != null the same value is also written there as a
-// real float64 right-hand side.
+// double) with zero imaginary part; if r64 != null the same value is also written there as
+// complex float64 (the mixed path's float64 residual, which starts at the right-hand side).
 template <typename T>
 hipError_t launch_proj_rhs(int64_t nd, int ns, int nvec, const double* psi, const double* U,
-                           const double* coeff, T* r0, double* b64, hipStream_t s);
+                           const double* coeff, T* r0, double* r64, hipStream_t s);
 
 // Batched COCG, one workgroup per system.  See cocg.hip for the layout.
 struct CocgLaunch {
@@ -103,7 +103,7 @@ struct CocgLaunch {
     int* status;           // nsys (0 ok, 1 not converged, 2 breakdown)
     bool fp32;             // mixed precision: state in complex64, reliable updates in FP64
     void* xlo;             // mixed: nsys x N_d complex64 partial solution
-    const double* b;       // mixed: nsys x N_d real right-hand side
+    double* rhi;           // mixed: nsys x N_d complex float64 residual (starts at the RHS)
     int* refinements;      // mixed: nsys (may be null)
     double refine_tol;     // mixed: residual drop that triggers a reliable update
 };

@@ -23,6 +23,9 @@ Array conventions (column-major blocks, x fastest on the grid):
   eps   (N_s,)       float64, ascending
   V0    (N_r, N_d)   float64, standard normal (row j = trial vector j)
 """
+import hashlib
+import json
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -158,8 +161,77 @@ def _chebyshev_filter(Hop, X, degree, a, b, a0):
     return Y
 
 
-def ground_state(shape, h, vloc, n_states, seed, tol=1e-10, degree=24, max_outer=200):
-    """Lowest n_states eigenpairs of H (Euclidean-orthonormal rows), plus residual norms."""
+class _SpectralHTorch:
+    """_SpectralH on a torch device (input generation only: FFT application of H)."""
+
+    def __init__(self, shape, h, vloc, device):
+        import torch
+        n0, n1, n2 = shape
+        self.shape = shape
+        kin = 0.5 * (_fd_symbol(n2, h)[:, None, None] + _fd_symbol(n1, h)[None, :, None]
+                     + _fd_symbol(n0, h)[None, None, :])
+        self.kin = torch.as_tensor(kin, device=device)
+        self.v = torch.as_tensor(vloc.reshape(n2, n1, n0), device=device)
+        self.ub = float(kin.max() + vloc.max())
+
+    def __call__(self, X):
+        import torch
+        n0, n1, n2 = self.shape
+        A = X.reshape(-1, n2, n1, n0)
+        F = torch.fft.fftn(A, dim=(1, 2, 3))
+        T = torch.fft.ifftn(F * self.kin[None], dim=(1, 2, 3)).real
+        return (T + self.v[None] * A).reshape(X.shape)
+
+    def upper_bound(self):
+        return self.ub
+
+
+def _ground_state_torch(shape, h, vloc, n_states, seed, tol, degree, max_outer, device):
+    """The Chebyshev-filtered subspace iteration of ground_state, run with torch on a device
+    (same start block, filter and Rayleigh-Ritz steps; rounding differs from the CPU run)."""
+    import torch
+    Hop = _SpectralHTorch(shape, h, vloc, device)
+    nd = int(np.prod(shape))
+    rng = np.random.default_rng(seed + 7919)
+    m = n_states + max(8, n_states // 4)
+    X = torch.as_tensor(rng.standard_normal((m, nd)), device=device)
+
+    def rr(X):
+        Q, _ = torch.linalg.qr(X.T)
+        Q = Q.T.contiguous()
+        HQ = Hop(Q)
+        Hs = Q @ HQ.T
+        Hs = 0.5 * (Hs + Hs.T)
+        ev, W = torch.linalg.eigh(Hs)
+        return ev, W.T @ Q, W.T @ HQ
+
+    def cheb(X, a, b, a0):
+        e, c = 0.5 * (b - a), 0.5 * (b + a)
+        sigma = e / (a0 - c)
+        tau = 2.0 / sigma
+        Y = (Hop(X) - c * X) * (sigma / e)
+        for _ in range(2, degree + 1):
+            s_new = 1.0 / (tau - sigma)
+            Ynew = (Hop(Y) - c * Y) * (2.0 * s_new / e) - (sigma * s_new) * X
+            X, Y, sigma = Y, Ynew, s_new
+        return Y
+
+    ev, X, HX = rr(X)
+    b = Hop.upper_bound()
+    for _ in range(max_outer):
+        X = cheb(X, float(ev[-1]), b, float(ev[0]))
+        ev, X, HX = rr(X)
+        res = torch.linalg.norm(HX - ev[:, None] * X, dim=1)
+        if float(res[:n_states + 1].max()) <= tol:
+            break
+    k = n_states + 1
+    return ev[:k].cpu().numpy(), X[:k].cpu().numpy(), res[:k].cpu().numpy()
+
+
+def ground_state(shape, h, vloc, n_states, seed, tol=1e-10, degree=24, max_outer=200,
+                 device=None):
+    """Lowest n_states eigenpairs of H (Euclidean-orthonormal rows), plus residual norms.
+    device: a torch device for the iterative solver (None: NumPy/SciPy on the host)."""
     Hop = _SpectralH(shape, h, vloc)
     nd = int(np.prod(shape))
     if nd <= 4096:
@@ -169,6 +241,8 @@ def ground_state(shape, h, vloc, n_states, seed, tol=1e-10, degree=24, max_outer
         X = vec.T
         R = Hop(X) - ev[:, None] * X
         return ev, X, np.linalg.norm(R, axis=1)
+    if device is not None:
+        return _ground_state_torch(shape, h, vloc, n_states, seed, tol, degree, max_outer, device)
     rng = np.random.default_rng(seed + 7919)
     m = n_states + max(8, n_states // 4)
     X = rng.standard_normal((m, nd))
@@ -183,9 +257,10 @@ def ground_state(shape, h, vloc, n_states, seed, tol=1e-10, degree=24, max_outer
     return ev[:n_states + 1], X[:n_states + 1], res[:n_states + 1]
 
 
-def make_cell(shape, h, centers, depths, sigmas, n_occ, seed, gap_min=1e-3, tol=1e-10):
+def make_cell(shape, h, centers, depths, sigmas, n_occ, seed, gap_min=1e-3, tol=1e-10,
+              device=None):
     vloc = gaussian_wells(shape, h, centers, depths, sigmas)
-    ev, X, res = ground_state(shape, h, vloc, n_occ + 1, seed, tol=tol)
+    ev, X, res = ground_state(shape, h, vloc, n_occ + 1, seed, tol=tol, device=device)
     dV = h ** 3
     psi = X[:n_occ] / np.sqrt(dV)
     # deterministic sign: largest-magnitude entry positive
@@ -229,9 +304,40 @@ def _random_wells(rng, n_wells, L, dlo, dhi, slo, shi):
     return centers, depths, sigmas
 
 
-def _cell_from_seed(shape, h, n_wells, n_occ, seed, fixed=None, lattice=None, tol=1e-10):
+def _cache_path(key):
+    d = os.environ.get("RPA_CELL_CACHE")
+    if not d:
+        return None
+    tag = hashlib.sha256(json.dumps(key, sort_keys=True).encode()).hexdigest()[:20]
+    return os.path.join(d, "cell_%s.npz" % tag)
+
+
+def _cell_from_seed(shape, h, n_wells, n_occ, seed, fixed=None, lattice=None, tol=1e-10,
+                    device=None):
     """Draw wells from `seed`; if the occupied/unoccupied gap is below 1e-3 Ha, move to the
-    next seed (recorded in meta['seed_used'])."""
+    next seed (recorded in meta['seed_used']).  With RPA_CELL_CACHE set to a directory, the
+    generated cell is stored there (plain arrays, .npz) and reused by later calls with the
+    same parameters."""
+    key = dict(shape=list(shape), h=h, n_wells=n_wells, n_occ=n_occ, seed=seed,
+               fixed=list(fixed) if fixed is not None else None, lattice=lattice, tol=tol,
+               solver="host" if device is None else "device")
+    path = _cache_path(key)
+    if path and os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            meta = json.loads(str(z["meta"]))
+            return Cell(tuple(int(v) for v in z["shape"]), float(z["h"]), z["vloc"].copy(),
+                        z["psi"].copy(), z["eps"].copy(), float(z["eps_next"]),
+                        float(z["residual"]), int(z["seed"]), meta)
+    cell = _cell_from_seed_compute(shape, h, n_wells, n_occ, seed, fixed, lattice, tol, device)
+    if path:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        np.savez(path, shape=np.asarray(cell.shape), h=cell.h, vloc=cell.vloc, psi=cell.psi,
+                 eps=cell.eps, eps_next=cell.eps_next, residual=cell.residual, seed=cell.seed,
+                 meta=json.dumps(cell.meta))
+    return cell
+
+
+def _cell_from_seed_compute(shape, h, n_wells, n_occ, seed, fixed, lattice, tol, device):
     L = [s * h for s in shape]
     for s in range(seed, seed + 50):
         rng = np.random.default_rng(s)
@@ -249,7 +355,8 @@ def _cell_from_seed(shape, h, n_wells, n_occ, seed, fixed=None, lattice=None, to
             sigmas = np.full(n_wells, fixed[1])
         else:
             centers, depths, sigmas = _random_wells(rng, n_wells, L, 1.0, 3.0, 0.8, 1.2)
-        cell = make_cell(shape, h, centers, depths, sigmas, n_occ, s, tol=tol)
+        cell = make_cell(shape, h, centers, depths, sigmas, n_occ, s, tol=tol, device=device)
+        cell.meta["solver"] = "host" if device is None else "device"
         if cell.meta["gap_ok"]:
             cell.meta.update(seed_requested=seed, seed_used=s, n_wells=len(centers))
             return cell
@@ -265,28 +372,29 @@ CONFIG_NAMES = {
 }
 
 
-def workload(k, tol=1e-10):
-    """The five synthetic workloads (sizes as described in the module docstring of DESIGN)."""
+def workload(k, tol=1e-10, device=None):
+    """The five synthetic workloads.  device: torch device for the ground-state solver of
+    the larger cells (None: host)."""
     if k == 0:
-        c = _cell_from_seed((12, 12, 12), 0.5, 2, 4, 1, fixed=(2.0, 1.0), tol=tol)
+        c = _cell_from_seed((12, 12, 12), 0.5, 2, 4, 1, fixed=(2.0, 1.0), tol=tol, device=device)
         return Workload(CONFIG_NAMES[0], [c], [16], np.array([1.0]), np.array([1.0]), 1e-10, 5,
                         [random_block(c.nd, 16, 1001)])
     om, W = frequency_rule(8, 1.0)
     if k == 1:
-        c = _cell_from_seed((24, 24, 24), 0.4, 16, 16, 2, tol=tol)
+        c = _cell_from_seed((24, 24, 24), 0.4, 16, 16, 2, tol=tol, device=device)
         return Workload(CONFIG_NAMES[1], [c], [64], om, W, 1e-8, 0, [random_block(c.nd, 64, 1002)])
     if k == 2:
-        c = _cell_from_seed((48, 48, 48), 0.35, 64, 64, 3, lattice=4, tol=tol)
+        c = _cell_from_seed((48, 48, 48), 0.35, 64, 64, 3, lattice=4, tol=tol, device=device)
         return Workload(CONFIG_NAMES[2], [c], [256], om, W, 1e-8, 0, [random_block(c.nd, 256, 1003)])
     if k == 3:
         grids = [20, 24, 28, 32, 36, 40]
         occ = [8, 12, 20, 28, 36, 48]
-        cells = [_cell_from_seed((g, g, g), 0.4, o, o, 100 + i, tol=tol)
+        cells = [_cell_from_seed((g, g, g), 0.4, o, o, 100 + i, tol=tol, device=device)
                  for i, (g, o) in enumerate(zip(grids, occ))]
         return Workload(CONFIG_NAMES[3], cells, [4 * o for o in occ], om, W, 1e-8, 0,
                         [random_block(c.nd, 4 * c.n_occ, 1100 + i) for i, c in enumerate(cells)])
     if k == 4:
-        c = _cell_from_seed((32, 32, 32), 0.4, 24, 32, 5, tol=tol)
+        c = _cell_from_seed((32, 32, 32), 0.4, 24, 32, 5, tol=tol, device=device)
         pts = np.sort(np.random.default_rng(2005).choice(c.nd, size=20, replace=False))
         return Workload(CONFIG_NAMES[4], [c], [128], om, W, 1e-8, 0, [random_block(c.nd, 128, 1005)],
                         extra=dict(fd_points=pts, fd_step=1e-4))

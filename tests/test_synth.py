@@ -26,3 +26,16 @@ def test_workload0_orbitals_against_oracle_stencil():
     wl2 = synth.workload(0)
     np.testing.assert_array_equal(wl2.V0[0], wl.V0[0])
     np.testing.assert_allclose(wl2.cells[0].vloc, c.vloc, rtol=0, atol=0)
+
+
+def test_device_ground_state_matches_host():
+    # the torch route of the Chebyshev-filtered solver (used to generate the large cells on the
+    # GPU) gives the same eigenpairs as the NumPy route, here on the CPU device
+    shape, h = (17, 17, 18), 0.45
+    rng = np.random.default_rng(4)
+    v = synth.gaussian_wells(shape, h, rng.uniform(0, 7, (3, 3)), [2.0, 1.5, 2.5], [1.0, 0.9, 1.1])
+    e1, X1, r1 = synth.ground_state(shape, h, v, 5, 3)
+    e2, X2, r2 = synth.ground_state(shape, h, v, 5, 3, device="cpu")
+    assert r1.max() < 1e-9 and r2.max() < 1e-9
+    np.testing.assert_allclose(e2, e1, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(np.abs(X2 @ X1.T), np.eye(6), atol=1e-8)
