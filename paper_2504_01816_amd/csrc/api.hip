@@ -177,7 +177,7 @@ int chunk_vectors(int ns, int nvec, const Opts& o) {
 
 int coeff_split(int64_t nd, int ns, int S) {
     const int tiles = ((ns + 63) / 64) * ((S + 63) / 64);
-    int sp = std::max(1, 1024 / std::max(1, tiles));
+    int sp = std::max(1, 2048 / std::max(1, tiles));
     sp = int(std::min<int64_t>(sp, std::max<int64_t>(1, nd / 1024)));
     return sp;
 }
@@ -211,7 +211,7 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
 
 int gram_split(int64_t nd, int m) {
     const int tiles = ((m + 63) / 64) * ((m + 63) / 64);
-    int sp = std::max(1, 512 / tiles);
+    int sp = std::max(1, 2048 / tiles);
     return int(std::min<int64_t>(sp, std::max<int64_t>(1, nd / 512)));
 }
 

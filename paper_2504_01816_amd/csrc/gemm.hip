@@ -10,6 +10,7 @@
 // Output tiles are oriented so that the 16 lanes sharing an MFMA row write contiguous
 // addresses.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -19,6 +20,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int NE = BM * BK / 256;   // tile elements loaded per thread and operand
 
 // Loader concept: double operator()(int row, int col, int z) const for A(m, k) or B(k, n),
 // plus static constexpr bool k_contig: true if consecutive k are contiguous in memory
@@ -42,36 +44,50 @@ __global__ __launch_bounds__(256) void gemm_f64(int M, int N, int K, int kchunk,
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
 
-    for (int k0 = kb; k0 < ke; k0 += BK) {
-        // A tile: BM x BK (m, k)
+    // Tile loads for step k0+BK are issued into registers before the MFMAs of step k0, so
+    // global (or L2) latency overlaps the matrix-core work.
+    double ra[NE], rb[NE];
+    // element e of this thread: (row, k) = (tid / BK + (256 / BK) e, tid % BK) when k is
+    // contiguous in memory, else (tid % 64, tid / 64 + 4 e)
+    auto load_tiles = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             int mm, kk;
             if constexpr (AL::k_contig) {
-                kk = tid & 15;
-                mm = (tid >> 4) + 16 * e;
+                kk = tid % BK;
+                mm = tid / BK + (256 / BK) * e;
             } else {
                 mm = tid & 63;
                 kk = (tid >> 6) + 4 * e;
             }
             const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < ke) ? al(gm, gk, z) : 0.0;
+            ra[e] = (gm < M && gk < ke) ? al(gm, gk, z) : 0.0;
         }
-        // B tile: BK x BN (k, n)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             int nn, kk;
             if constexpr (BL::k_contig) {
-                kk = tid & 15;
-                nn = (tid >> 4) + 16 * e;
+                kk = tid % BK;
+                nn = tid / BK + (256 / BK) * e;
             } else {
                 nn = tid & 63;
                 kk = (tid >> 6) + 4 * e;
             }
             const int gn = n0 + nn, gk = k0 + kk;
-            Bs[kk][nn] = (gn < N && gk < ke) ? bl(gk, gn, z) : 0.0;
+            rb[e] = (gn < N && gk < ke) ? bl(gk, gn, z) : 0.0;
+        }
+    };
+    if (kb < ke) load_tiles(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            if constexpr (AL::k_contig) As[tid % BK][tid / BK + (256 / BK) * e] = ra[e];
+            else As[(tid >> 6) + 4 * e][tid & 63] = ra[e];
+            if constexpr (BL::k_contig) Bs[tid % BK][tid / BK + (256 / BK) * e] = rb[e];
+            else Bs[(tid >> 6) + 4 * e][tid & 63] = rb[e];
         }
         __syncthreads();
+        if (k0 + BK < ke) load_tiles(k0 + BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             double af[2], bf[2];
@@ -156,12 +172,10 @@ struct StoreRhs {  // r0[s][r] = -(psi_n u_j - acc), complex with zero imaginary
     __device__ void operator()(int s, int r, int, double acc) const {
         const int n = s % ns, j = s / ns;
         const double b = psi[r + nd * n] * U[r + nd * j] - acc;
-        r0[2 * (int64_t(s) * nd + r)] = T(-b);
-        r0[2 * (int64_t(s) * nd + r) + 1] = T(0);
-        if (r64) {   // the same right-hand side as complex float64
-            r64[2 * (int64_t(s) * nd + r)] = -b;
-            r64[2 * (int64_t(s) * nd + r) + 1] = 0.0;
-        }
+        using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+        reinterpret_cast<T2*>(r0)[int64_t(s) * nd + r] = T2{T(-b), T(0)};
+        if (r64)   // the same right-hand side as complex float64
+            reinterpret_cast<double2*>(r64)[int64_t(s) * nd + r] = double2{-b, 0.0};
     }
 };
 

@@ -48,13 +48,18 @@ def cmd_copy(args):
     print(json.dumps({"copy_bytes": n, "reps": args.reps}), file=sys.stderr)
 
 
+def _workload(args):
+    from . import synth
+    return synth.workload(args.config, device="cuda:0" if args.gen_device else None)
+
+
 def cmd_apply(args):
     import torch
 
     from . import api, synth
     from . import lib as L
 
-    wl = synth.workload(args.config)
+    wl = _workload(args)
     c = wl.cells[0]
     dc = api.device_cell(c, "cuda:0")
     nvec = args.nvec or wl.n_r[0]
@@ -76,6 +81,76 @@ def cmd_apply(args):
     if args.out:
         with open(args.out, "w") as f:
             json.dump(tot, f)
+
+
+def cmd_subspace(args):
+    """One (or --iters) subspace iteration step(s) at one frequency: every stage of the path
+    (two nu^1/2 applications, projector, COCG, Delta rho, projection, energy, Cholesky-QR)."""
+    import torch
+
+    from . import api
+    from . import lib as L
+
+    wl = _workload(args)
+    c = wl.cells[0]
+    dc = api.device_cell(c, "cuda:0")
+    prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
+    Q, _ = torch.linalg.qr(torch.tensor(wl.V0[0], device="cuda:0").T)   # orthonormal start
+    V = Q.T.contiguous()
+    m = args.omega_index
+    r = api.rpa_subspace_iter(dc, float(wl.omegas[m]), float(wl.weights[m]), V,
+                              dict(precision=prec, cocg_tol=wl.cocg_tol, subspace_iters=args.iters,
+                                   ec_tol=0.0), want_ritz=False, want_saved=False)
+    torch.cuda.synchronize()
+    out = dict(workload=wl.name, precision=args.precision, omega=float(wl.omegas[m]),
+               iters=args.iters, E=r["E"], nd=c.nd, n=list(c.shape), ns=c.n_occ, nr=wl.n_r[0],
+               stats=r["stats"])
+    print(json.dumps(out), file=sys.stderr)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f)
+
+
+# stage of the path -> (substring of the kernel name, flops of one subspace step)
+def _stage_flops(nd, n, ns, nr):
+    return [
+        ("projector coefficients c = dV Psi^T (psi_n u_j)", "PsiT", 2.0 * nd * ns * ns * nr),
+        ("projected right-hand sides b' = b - Psi c (HBM-bound: writes the COCG start vectors)",
+         "CoeffT", 2.0 * nd * ns * ns * nr),
+        ("nu^1/2 Kronecker transforms (2 applications x 6 passes; HBM-bound, n/8 flop/B)", "Axis",
+         2 * sum(4.0 * a * nd * nr for a in n)),
+        ("projection C = V^T R and Gram M = R^T R", "ColT", 2 * 2.0 * nd * nr * nr),
+        ("Cholesky-QR rotation V = R L^-T", "SmallT", 2.0 * nd * nr * nr),
+    ]
+
+
+def cmd_stages(args):
+    """Per-stage kernel time and achieved FLOP/s of a traced `subspace` run (FP64 MFMA peak
+    78.6 TFLOP/s for the GEMM stages)."""
+    info = json.load(open(args.run))
+    fn = args.trace
+    if os.path.isdir(fn):
+        fn = sorted(glob.glob(os.path.join(fn, "**", "*kernel_trace.csv"), recursive=True))[0]
+    rows = list(csv.DictReader(open(fn)))
+    dur = {}
+    for r in rows:
+        d = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
+        dur.setdefault(r["Kernel_Name"], []).append(d)
+    it = info["iters"]
+    print("| stage | kernels matched | dispatches | time ms | flop | TFLOP/s | of 78.6 |")
+    print("|---|---|---|---|---|---|---|")
+    for name, key, fl in _stage_flops(info["nd"], info["n"], info["ns"], info["nr"]):
+        ks = [k for k in dur if key in k]
+        t = sum(sum(dur[k]) for k in ks)
+        nds = sum(len(dur[k]) for k in ks)
+        f = fl * it
+        print("| %s | `%s` | %d | %.3f | %.3g | %.2f | %.1f%% |" % (
+            name, key, nds, t * 1e3, f, f / t / 1e12 if t else 0, 100 * f / t / 78.6e12 if t else 0))
+    for key, label in (("cocg_wg", "COCG"), ("drho", "Delta rho"), ("reduce_parts", "split-K reductions"),
+                       ("energy_kernel", "energy (Cholesky of I - C)"), ("chol_inv", "Cholesky + inverse")):
+        ks = [k for k in dur if key in k]
+        t = sum(sum(dur[k]) for k in ks)
+        print("| %s | `%s` | %d | %.3f | | | |" % (label, key, sum(len(dur[k]) for k in ks), t * 1e3))
 
 
 def read_counters(path):
@@ -166,11 +241,22 @@ def main():
     c.add_argument("--mib", type=int, default=1024)
     c.add_argument("--reps", type=int, default=4)
     a = sub.add_parser("apply")
+    a.add_argument("--gen-device", action="store_true", help="ground states computed on the GPU")
     a.add_argument("--config", type=int, default=1)
     a.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     a.add_argument("--omega-index", type=int, default=-1, help="-1: every frequency")
     a.add_argument("--nvec", type=int, default=0)
     a.add_argument("--out", default="")
+    ss = sub.add_parser("subspace")
+    ss.add_argument("--gen-device", action="store_true")
+    ss.add_argument("--config", type=int, default=2)
+    ss.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ss.add_argument("--omega-index", type=int, default=0)
+    ss.add_argument("--iters", type=int, default=1)
+    ss.add_argument("--out", default="")
+    st = sub.add_parser("stages")
+    st.add_argument("trace")
+    st.add_argument("--run", required=True, help="JSON written by `subspace --out`")
     s = sub.add_parser("summarize")
     s.add_argument("csv")
     s.add_argument("--match", default="")
@@ -188,8 +274,8 @@ def main():
     t.add_argument("--apply-stats", required=True)
     t.add_argument("--write", default="")
     args = ap.parse_args()
-    {"copy": cmd_copy, "apply": cmd_apply, "summarize": cmd_summarize, "kstats": cmd_kstats,
-     "traffic": cmd_traffic}[args.cmd](args)
+    {"copy": cmd_copy, "apply": cmd_apply, "subspace": cmd_subspace, "stages": cmd_stages,
+     "summarize": cmd_summarize, "kstats": cmd_kstats, "traffic": cmd_traffic}[args.cmd](args)
 
 
 if __name__ == "__main__":
