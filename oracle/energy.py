@@ -24,7 +24,7 @@ def chi0_tilde_apply(V, vloc, psi, eps, omega, shape, h, tol, max_iter):
 
 
 def rpa_energy(vloc, psi, eps, shape, h, V0, omegas, weights, cocg_tol, cocg_max_iter,
-               subspace_iters, ec_tol=0.0, mode="warm"):
+               subspace_iters, ec_tol=0.0, mode="warm", sq_order=0):
     """Full E_c.  subspace_iters is the fixed count (ec_tol <= 0) or the cap (ec_tol > 0);
     it may be a scalar or one value per frequency.  Returns a dict with E_c, per-frequency
     energies, iteration counts, and the saved (V_m, C_m) per frequency."""
@@ -42,7 +42,7 @@ def rpa_energy(vloc, psi, eps, shape, h, V0, omegas, weights, cocg_tol, cocg_max
         def apply(Vb, om=om):
             return chi0_tilde_apply(Vb, vloc, psi, eps, om, shape, h, cocg_tol, cocg_max_iter)
 
-        out = subspace_iteration(apply, V, float(weights[m]), int(its[m]), ec_tol)
+        out = subspace_iteration(apply, V, float(weights[m]), int(its[m]), ec_tol, sq_order)
         res["E_freq"][m] = out["E"]
         res["n_iter"][m] = out["n_iter"]
         res["V_saved"].append(out["V_saved"])

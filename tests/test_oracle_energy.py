@@ -1,5 +1,7 @@
 """Pins for the subspace iteration, the energy assembly and the frequency rule
 (Eqs. 6 and 10, Algorithm 1, Sec. 3)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -123,3 +125,57 @@ def test_warm_and_independent_modes_agree_at_convergence(cell6):
     assert abs(a["E_c"] - b["E_c"]) <= 1e-9 * abs(a["E_c"])
     # warm starts need fewer subspace iterations at the lower frequencies
     assert a["n_iter"][1:].sum() <= b["n_iter"][1:].sum()
+
+
+# ---------------------------------------------------------------- Gauss spectral quadrature
+def _spd_neg(m, seed, lo=-0.9, hi=-0.01):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    lam = rng.uniform(lo, hi, m)
+    return (Q * lam) @ Q.T, lam
+
+
+def test_sq_full_order_equals_ritz_sum():
+    # with N_o >= m the Lanczos tridiagonal of every e_r spans its Krylov space: Gauss SQ is
+    # then exact, tr g(C) = sum_k g(mu_k)
+    C, lam = _spd_neg(9, 1)
+    assert abs(subspace.gauss_sq_trace(C, 9, subspace.g) - np.sum(subspace.g(lam))) < 1e-13 * abs(np.sum(subspace.g(lam)))
+
+
+def test_sq_exact_for_polynomials_up_to_degree_2No_minus_1():
+    # an N_o-node Gauss rule integrates polynomials of degree <= 2 N_o - 1 exactly, and not 2 N_o
+    C, lam = _spd_neg(12, 2, -1.0, 1.0)
+    for n_o in (2, 3, 4):
+        d = 2 * n_o - 1
+        p = lambda x, d=d: (1.0 + x) ** d
+        exact = np.sum(p(lam))
+        assert abs(subspace.gauss_sq_trace(C, n_o, p) - exact) < 1e-11 * abs(exact)
+        q = lambda x, d=d: (1.0 + x) ** (d + 1)
+        assert abs(subspace.gauss_sq_trace(C, n_o, q) - np.sum(q(lam))) > 1e-8
+
+
+def test_sq_converges_monotonically_from_above():
+    # every even derivative of g(x) = ln(1-x) + x is negative, so each Gauss rule over-
+    # estimates e_r^T g(C) e_r and the error shrinks with the order: E(N_o) decreases to the
+    # Ritz sum, the trend of Table 1 (|E_c| grows with N_o, converged by N_o = 4)
+    C, lam = _spd_neg(16, 3)
+    exact = np.sum(subspace.g(lam))
+    vals = [subspace.gauss_sq_trace(C, n, subspace.g) for n in (1, 2, 3, 4, 6)]
+    assert all(v >= exact - 1e-15 for v in vals)
+    assert all(vals[i + 1] <= vals[i] + 1e-15 for i in range(len(vals) - 1))
+    assert abs(vals[3] - exact) < 1e-4 * abs(exact)
+    tab = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "sq_order_table1.txt"),
+                     usecols=(1, 2, 3))
+    assert np.all(np.diff(tab, axis=1) <= 0)
+
+
+def test_sq_lanczos_tridiagonal_matches_definition():
+    # J from the Lanczos recurrence reproduces C's action on the Krylov basis: the first
+    # moments e_r^T C^k e_r equal (J^k)_11 for k <= 2 N_o - 1
+    C, _ = _spd_neg(10, 4)
+    a, b = subspace.lanczos_tridiagonal(C, 3, 4)
+    J = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    e = np.zeros(10)
+    e[3] = 1.0
+    for k in range(1, 8):
+        assert abs(e @ np.linalg.matrix_power(C, k) @ e - np.linalg.matrix_power(J, k)[0, 0]) < 1e-12
