@@ -38,6 +38,8 @@ def parse():
                     help="warm: frequencies in sequence, each started from the previous one's "
                          "subspace (Algorithm 1); independent: every frequency from V0, all "
                          "frequencies batched into one chi0 launch per subspace iteration")
+    ap.add_argument("--sq-order", type=int, default=0,
+                    help="energy by Gauss spectral quadrature of this order (0: Rayleigh-Ritz)")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ec-tol", type=float, default=1e-8)
@@ -112,7 +114,7 @@ def main():
     V0 = [torch.tensor(v, device=dev) for v in wl.V0]
     prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
     opts = dict(precision=prec, cocg_tol=wl.cocg_tol, subspace_iters=args.max_subspace,
-                ec_tol=args.ec_tol,
+                ec_tol=args.ec_tol, sq_order=args.sq_order,
                 freq_mode=L.RPA_WARM if args.freq_mode == "warm" else L.RPA_INDEPENDENT)
     if wl.subspace_iters > 0:
         opts.update(subspace_iters=wl.subspace_iters, ec_tol=0.0)
@@ -181,7 +183,7 @@ def main():
                    "n_occ": wl.cells[0].n_occ, "n_r": wl.n_r[0], "n_freq": len(wl.omegas),
                    "cocg_tol": wl.cocg_tol, "ec_tol": opts["ec_tol"],
                    "backward": not args.no_backward, "precision": args.precision,
-                   "freq_mode": args.freq_mode},
+                   "freq_mode": args.freq_mode, "sq_order": args.sq_order},
         "time_to_ec_s": float(np.mean([s["fwd_s"] for s in steps])),
         "backward_s": float(np.mean([s["bwd_s"] for s in steps])),
         "E_c": steps[-1]["E"],

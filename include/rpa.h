@@ -92,6 +92,13 @@ typedef struct rpa_options {
                                 float64 refinements (reliable updates), default 0.1 */
     int32_t max_systems;     /* cap on Sternheimer systems in flight (0 = library choice) */
     int32_t flags;           /* reserved, 0 */
+    int32_t sq_order;        /* 0 (default): E_{c,m} from the Ritz values of C (exact
+                                Rayleigh-Ritz, via ln det(I - C) + tr C); 1..32: Gauss
+                                spectral quadrature of that order on C (Sec. 3, Algorithm 1:
+                                Lanczos from every e_r, nodes and weights from the
+                                tridiagonal).  The backward always differentiates the
+                                Rayleigh-Ritz energy of the saved subspaces, which the SQ
+                                energy converges to as the order grows. */
 } rpa_options;
 
 /* Counters accumulated by a call (added to the struct's current contents). */

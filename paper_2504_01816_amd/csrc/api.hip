@@ -48,6 +48,7 @@ struct Opts {
     double ec_tol = 1e-8;
     double refine_tol = 1e-1;
     int max_systems = 0;
+    int sq_order = 0;
 };
 
 int fail(int code, const std::string& msg) {
@@ -66,6 +67,7 @@ int read_opts(const rpa_options* o, Opts* out) {
         d.ec_tol = o->ec_tol;
         d.refine_tol = o->refine_tol;
         d.max_systems = o->max_systems;
+        d.sq_order = o->sq_order;
     }
     if (d.precision != RPA_FP64 && d.precision != RPA_MIXED)
         return fail(RPA_EINVAL, "options.precision must be RPA_FP64 or RPA_MIXED");
@@ -79,6 +81,8 @@ int read_opts(const rpa_options* o, Opts* out) {
     if (!(d.refine_tol > 0.0 && d.refine_tol < 1.0))
         return fail(RPA_EINVAL, "options.refine_tol must be in (0, 1)");
     if (d.max_systems < 0) return fail(RPA_EINVAL, "options.max_systems must be >= 0");
+    if (d.sq_order < 0 || d.sq_order > 32)
+        return fail(RPA_EINVAL, "options.sq_order must be in [0, 32]");
     *out = d;
     return RPA_OK;
 }
@@ -524,7 +528,11 @@ int subspace_iter(const rpa_cell* cell, const Grid& g, double omega, double weig
         RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, b.D, b.R, s));
         RPA_HIP(launch_gram(nd, nr, V, b.R, b.part, b.gsplit, b.C, s));
         RPA_HIP(launch_symmetrize(nr, b.C, s));
-        RPA_HIP(launch_energy_logdet(nr, b.C, weight / (2.0 * M_PI), b.ework, b.escal, b.info, s));
+        if (o.sq_order > 0)
+            RPA_HIP(launch_sq_energy(nr, b.C, o.sq_order, weight / (2.0 * M_PI), b.ework, b.escal,
+                                     b.info, s));
+        else
+            RPA_HIP(launch_energy_logdet(nr, b.C, weight / (2.0 * M_PI), b.ework, b.escal, b.info, s));
         int info = 0;
         RPA_HIP(hipMemcpyAsync(&E, b.escal, sizeof(double), hipMemcpyDeviceToHost, s));
         RPA_HIP(hipMemcpyAsync(&info, b.info, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -617,8 +625,12 @@ int energy_batched(const rpa_cell* cell, int nr, int nfreq, const double* omega,
             double* C = b.C + f * sq;
             RPA_HIP(launch_gram(nd, nr, b.P + a * blk, b.R + a * blk, b.part, b.gsplit, C, s));
             RPA_HIP(launch_symmetrize(nr, C, s));
-            RPA_HIP(launch_energy_logdet(nr, C, weight[f] / (2.0 * M_PI), b.ework, b.escal + 8 * f,
-                                         b.info + 8 * f, s));
+            if (o.sq_order > 0)
+                RPA_HIP(launch_sq_energy(nr, C, o.sq_order, weight[f] / (2.0 * M_PI), b.ework,
+                                         b.escal + 8 * f, b.info + 8 * f, s));
+            else
+                RPA_HIP(launch_energy_logdet(nr, C, weight[f] / (2.0 * M_PI), b.ework,
+                                             b.escal + 8 * f, b.info + 8 * f, s));
             RPA_HIP(launch_gram(nd, nr, b.R + a * blk, b.R + a * blk, b.part, b.gsplit, b.M + f * sq, s));
             RPA_HIP(launch_chol_inv(nr, b.M + f * sq, b.L + f * sq, b.T + f * sq, b.info + 8 * f + 1, s));
         }
@@ -710,6 +722,7 @@ int rpa_default_options(rpa_options* opt) {
     opt->refine_tol = d.refine_tol;
     opt->max_systems = d.max_systems;
     opt->flags = 0;
+    opt->sq_order = d.sq_order;
     return RPA_OK;
 }
 

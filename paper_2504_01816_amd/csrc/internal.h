@@ -130,6 +130,10 @@ hipError_t launch_chol_inv(int m, const double* M, double* L, double* T, int* in
 // E = scale * (ln det(I - C) + tr C) via Cholesky of I - C; out[0] = E, info[0] as above.
 hipError_t launch_energy_logdet(int m, const double* C, double scale, double* work,
                                 double* out, int* info, hipStream_t s);
+// Gauss spectral quadrature of order n_o (1..32): E = scale * sum_r e_r^T g(C) e_r by n_o
+// Lanczos steps from each e_r; work >= m + 1 doubles; out[0] = E, info[0] = 0 (1: not finite).
+hipError_t launch_sq_energy(int m, const double* C, int n_o, double scale, double* work,
+                            double* out, int* info, hipStream_t s);
 // Symmetric eigen-decomposition by cyclic Jacobi: A (m x m) copied to work; eigenvalues
 // ascending into w, eigenvectors (columns) into Y if Y != nullptr.
 hipError_t launch_syevj(int m, const double* A, double* work, double* w, double* Y,

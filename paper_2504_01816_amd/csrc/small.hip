@@ -269,7 +269,172 @@ __global__ void copy_kernel(int64_t n, const double* src, double* dst) {
     if (i < n) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------------ Gauss spectral quadrature
+// E = scale * sum_r sum_t Q_r(1,t)^2 g(lambda_t): for each standard basis vector e_r, n_o
+// Lanczos steps on C give the tridiagonal J_r, whose eigenvalues (nodes) and squared first
+// eigenvector components (weights) form the Gauss rule for e_r^T g(C) e_r (Sec. 3,
+// Algorithm 1, SQ method).  One workgroup per r; the m x m matrix C is read once per step
+// (coalesced along columns); Lanczos stops early when beta <= 1e-14 max|C| (exhausted Krylov
+// space).  The small tridiagonal eigenproblem is solved by cyclic Jacobi on one wave.
+
+__global__ __launch_bounds__(256) void absmax_kernel(int64_t n, const double* a, double* out) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v = fmax(v, fabs(a[i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+        out[0] = m;
+    }
+}
+
+constexpr int SQ_MAX = 32;   // largest quadrature order
+
+__device__ double block_sum256(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += red[w];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void sq_lanczos_kernel(int m, const double* C, int n_o,
+                                                         const double* cmax, double* part) {
+    extern __shared__ double sh[];
+    double* q = sh;             // m
+    double* qp = sh + m;        // m
+    double* w = sh + 2 * m;     // m
+    __shared__ double red[4];
+    __shared__ double A[SQ_MAX * SQ_MAX], Vv[SQ_MAX * SQ_MAX];
+    __shared__ int kdim;
+    const int r = blockIdx.x, tid = threadIdx.x;
+    for (int i = tid; i < m; i += 256) {
+        q[i] = (i == r) ? 1.0 : 0.0;
+        qp[i] = 0.0;
+    }
+    for (int i = tid; i < SQ_MAX * SQ_MAX; i += 256) A[i] = 0.0;
+    if (tid == 0) kdim = n_o;
+    __syncthreads();
+    const double tiny = 1e-14 * fmax(cmax[0], 1e-300);
+    double beta = 0.0;
+    for (int k = 0; k < n_o; ++k) {
+        // w = C q - beta q_prev
+        for (int i = tid; i < m; i += 256) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += C[i + int64_t(m) * j] * q[j];
+            w[i] = s - beta * qp[i];
+        }
+        __syncthreads();
+        double pa = 0.0;
+        for (int i = tid; i < m; i += 256) pa += q[i] * w[i];
+        const double alpha = block_sum256(pa, red);
+        for (int i = tid; i < m; i += 256) w[i] -= alpha * q[i];
+        if (tid == 0) A[k + SQ_MAX * k] = alpha;
+        __syncthreads();
+        if (k == n_o - 1) break;
+        double pb = 0.0;
+        for (int i = tid; i < m; i += 256) pb += w[i] * w[i];
+        beta = sqrt(block_sum256(pb, red));
+        if (!(beta > tiny)) {
+            if (tid == 0) kdim = k + 1;
+            __syncthreads();
+            break;
+        }
+        for (int i = tid; i < m; i += 256) {
+            qp[i] = q[i];
+            q[i] = w[i] / beta;
+        }
+        if (tid == 0) {
+            A[k + 1 + SQ_MAX * k] = beta;
+            A[k + SQ_MAX * (k + 1)] = beta;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // cyclic Jacobi on the kdim x kdim tridiagonal (one thread; kdim <= 32)
+    if (tid == 0) {
+        const int n = kdim;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Vv[i + SQ_MAX * j] = (i == j) ? 1.0 : 0.0;
+        for (int sweep = 0; sweep < 100; ++sweep) {
+            double off = 0.0, dia = 0.0;
+            for (int i = 0; i < n; ++i) {
+                dia += A[i + SQ_MAX * i] * A[i + SQ_MAX * i];
+                for (int j = i + 1; j < n; ++j) off += A[i + SQ_MAX * j] * A[i + SQ_MAX * j];
+            }
+            if (!(off > 1e-30 * dia)) break;
+            for (int p = 0; p < n - 1; ++p)
+                for (int qq = p + 1; qq < n; ++qq) {
+                    const double apq = A[p + SQ_MAX * qq];
+                    if (apq == 0.0) continue;
+                    const double app = A[p + SQ_MAX * p], aqq = A[qq + SQ_MAX * qq];
+                    const double theta = (aqq - app) / (2.0 * apq);
+                    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                    const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                    for (int k = 0; k < n; ++k) {   // A <- A G (columns p, q)
+                        const double akp = A[k + SQ_MAX * p], akq = A[k + SQ_MAX * qq];
+                        A[k + SQ_MAX * p] = c * akp - sn * akq;
+                        A[k + SQ_MAX * qq] = sn * akp + c * akq;
+                    }
+                    for (int k = 0; k < n; ++k) {   // A <- G^T A (rows p, q)
+                        const double apk = A[p + SQ_MAX * k], aqk = A[qq + SQ_MAX * k];
+                        A[p + SQ_MAX * k] = c * apk - sn * aqk;
+                        A[qq + SQ_MAX * k] = sn * apk + c * aqk;
+                    }
+                    for (int k = 0; k < n; ++k) {   // V <- V G
+                        const double vkp = Vv[k + SQ_MAX * p], vkq = Vv[k + SQ_MAX * qq];
+                        Vv[k + SQ_MAX * p] = c * vkp - sn * vkq;
+                        Vv[k + SQ_MAX * qq] = sn * vkp + c * vkq;
+                    }
+                }
+        }
+        double e = 0.0;
+        for (int t = 0; t < n; ++t) {
+            const double lam = A[t + SQ_MAX * t], q0 = Vv[0 + SQ_MAX * t];
+            e += q0 * q0 * (log1p(-lam) + lam);
+        }
+        part[r] = e;
+    }
+}
+
+// out[0] = scale * sum_r part[r] in a fixed order (deterministic); info[0] = 0, or 1 if the
+// sum is not finite
+__global__ __launch_bounds__(256) void sq_sum_kernel(int m, const double* part, double scale,
+                                                     double* out, int* info) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) v += part[i];
+    const double s = block_sum256(v, red);
+    if (threadIdx.x == 0) {
+        out[0] = scale * s;
+        info[0] = isfinite(s) ? 0 : 1;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_sq_energy(int m, const double* C, int n_o, double scale, double* work,
+                            double* out, int* info, hipStream_t s) {
+    if (n_o < 1 || n_o > SQ_MAX) return hipErrorInvalidValue;
+    double* cmax = work;
+    double* part = work + 1;
+    hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, int64_t(m) * m, C, cmax);
+    const size_t sh = 3 * size_t(m) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sq_lanczos_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(sh));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sq_lanczos_kernel, dim3(m), dim3(256), sh, s, m, C, n_o, cmax, part);
+    hipLaunchKernelGGL(sq_sum_kernel, dim3(1), dim3(256), 0, s, m, part, scale, out, info);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_symmetrize(int m, double* C, hipStream_t s) {
     hipLaunchKernelGGL(symmetrize_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, m, C);

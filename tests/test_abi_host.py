@@ -3,6 +3,7 @@ and validates arguments before touching a device (no GPU needed)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -33,10 +34,30 @@ def test_every_declared_symbol_is_exported(so):
         assert hasattr(so, n), n
 
 
-def test_struct_layouts_match_header():
-    assert ctypes.sizeof(L.RpaCell) == 48
-    assert ctypes.sizeof(L.RpaOptions) == 48
-    assert ctypes.sizeof(L.RpaStats) == 64
+def test_struct_layouts_match_header(tmp_path):
+    # compile a probe against include/rpa.h with the host C compiler and compare every
+    # field offset and struct size with the ctypes mirror
+    structs = {"rpa_cell": L.RpaCell, "rpa_options": L.RpaOptions, "rpa_stats": L.RpaStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rpa.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n"):
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def _cell(n=(12, 12, 12), n_occ=4, h=0.5, eps=None):
@@ -113,6 +134,9 @@ def test_chi0_rejects_bad_scalars_and_workspace(so):
                              None) == L.RPA_EWORKSPACE       # misaligned
     assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5000, 1024,
                              None) == L.RPA_EWORKSPACE       # too small
+    bad = L.default_options(sq_order=33)
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(bad), None,
+                             0x5000, 1 << 30, None) == L.RPA_EINVAL
     o = L.default_options(cocg_tol=0.0)
     assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(o), None,
                              0x5000, 1 << 30, None) == L.RPA_EINVAL

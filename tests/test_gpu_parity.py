@@ -288,3 +288,46 @@ def test_independent_batched_stops_each_frequency_on_its_own(small3):
                              dict(opts, subspace_iters=int(its[m]), ec_tol=0.0))
         assert abs(one["E_c"][0] - res["E_freq"][0][m]) <= 1e-9 * abs(one["E_c"][0])
 
+
+
+# ---------------------------------------------------------------------------- Gauss SQ energy
+@pytest.mark.parametrize("n_o", [2, 4, 16])
+def test_sq_energy_of_the_gpu_projected_matrix(wl0, dc0, n_o):
+    # the GPU's SQ energy of its own C against the oracle's SQ on that same C; at order 16
+    # (= N_r) the rule is exact and equals the Rayleigh-Ritz energy
+    say("SQ energy, order", n_o)
+    from oracle.subspace import chol_orthonormalize
+    V = torch.tensor(chol_orthonormalize(wl0.V0[0].T).T.copy(), device=DEV)
+    r = api.rpa_subspace_iter(dc0, 1.0, 0.7, V.clone(), dict(cocg_tol=1e-10, subspace_iters=1,
+                                                            ec_tol=0.0, sq_order=n_o))
+    C = r["C"].cpu().numpy()
+    ref = osub.sq_energy(C, 0.7, n_o)
+    assert abs(r["E"] - ref) <= 1e-12 * abs(ref)
+    rr = 0.7 / (2 * np.pi) * np.sum(osub.g(np.linalg.eigvalsh(C)))
+    if n_o == 16:
+        assert abs(r["E"] - rr) <= 1e-12 * abs(rr)
+    else:
+        assert r["E"] >= rr - 1e-15      # Gauss SQ approaches from above (g'' < 0)
+
+
+def test_energy_with_sq_matches_oracle(wl0, dc0):
+    say("rpa_energy 12^3 with SQ order 3")
+    c = wl0.cells[0]
+    ref = oenergy.rpa_energy(c.vloc, c.psi.T, c.eps, c.shape, c.h, wl0.V0[0].T, wl0.omegas,
+                             wl0.weights, 1e-10, 5000, 5, sq_order=3)
+    res = api.rpa_energy(dc0, 16, wl0.omegas, wl0.weights, [torch.tensor(wl0.V0[0], device=DEV)],
+                         dict(cocg_tol=1e-10, subspace_iters=5, ec_tol=0.0, sq_order=3))
+    assert res["status"] == 0
+    assert abs(res["E_c"][0] - ref["E_c"]) <= 1e-9 * abs(ref["E_c"])
+
+
+def test_batched_frequencies_with_sq_match_oracle(small3):
+    c, om, W, V0, _ = small3
+    say("batched frequencies with SQ order 2")
+    ref = oenergy.rpa_energy(c.vloc, c.psi.T, c.eps, c.shape, c.h, V0.T, om, W, 1e-11, 5000, 3,
+                             mode="independent", sq_order=2)
+    dc = api.device_cell(c, DEV)
+    res = api.rpa_energy(dc, 6, om, W, [torch.tensor(V0, device=DEV)],
+                         dict(cocg_tol=1e-11, subspace_iters=3, ec_tol=0.0, freq_mode=INDEPENDENT,
+                              sq_order=2))
+    np.testing.assert_allclose(res["E_freq"][0], ref["E_freq"], rtol=1e-9)
