@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ec-tol", type=float, default=1e-8)
     ap.add_argument("--max-subspace", type=int, default=50)
+    ap.add_argument("--compare", default="batched", choices=["none", "batched"],
+                    help="batched: after the timed steps, also time one step (after one warm-up) "
+                         "of the batched-frequency path in FP64 and in mixed precision")
     return ap.parse_args()
 
 
@@ -119,7 +122,7 @@ def main():
     if wl.subspace_iters > 0:
         opts.update(subspace_iters=wl.subspace_iters, ec_tol=0.0)
 
-    def step():
+    def step(opts=opts):
         st = {"fwd_s": 0.0, "bwd_s": 0.0, "applies": 0, "cocg_ms": 0.0, "point_iters": 0.0,
               "launches": 0, "iters": None, "E": None}
         torch.cuda.synchronize()
@@ -198,6 +201,34 @@ def main():
                      "alg_bytes_per_point_iter": ALG_BYTES[args.precision],
                      "cocg_share_of_step": cocg_ms * 1e-3 / T},
     }
+    if args.compare == "batched":
+        # the metric's comparison: the batched-frequency path (every frequency from V0, all of
+        # them in one COCG launch per subspace iteration) in FP64 and with complex64 state and
+        # float64 reliable updates, same inputs and stopping rule
+        comp = {}
+        e_ref = None
+        for name, prec_c in (("fp64_batched", L.RPA_FP64), ("mixed_batched", L.RPA_MIXED)):
+            o2 = dict(opts, precision=prec_c, freq_mode=L.RPA_INDEPENDENT)
+            step(o2)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            s2 = step(o2)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+            ab = ALG_BYTES["fp64" if prec_c == L.RPA_FP64 else "mixed"]
+            comp[name] = {"chi0_block_applies_per_s": s2["applies"] / t,
+                          "time_to_ec_s": s2["fwd_s"], "backward_s": s2["bwd_s"],
+                          "E_c": s2["E"], "subspace_iters": s2["iters"],
+                          "cocg_alg_GBs": ab * s2["point_iters"] / (s2["cocg_ms"] * 1e-3) / 1e9}
+            if e_ref is None:
+                e_ref = s2["E"]
+            else:
+                comp[name]["E_c_rel_diff_vs_fp64_batched"] = [
+                    abs(a - b) / abs(b) for a, b in zip(s2["E"], e_ref)]
+            print("[bench] compare %s: %.2f s fwd, %.2f applies/s, E_c %s" % (
+                name, s2["fwd_s"], comp[name]["chi0_block_applies_per_s"], s2["E"]),
+                file=sys.stderr, flush=True)
+        out["compare"] = comp
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(wl)

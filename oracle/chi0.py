@@ -40,7 +40,7 @@ def build_rhs(U, psi, dV):
 
 
 def chi0_apply(U, vloc, psi, eps, omega, shape, h, tol, max_iter,
-               chunk=256, return_solutions=False):
+               chunk=256, return_solutions=False, bc="periodic"):
     """chi0(i omega) U by DFPT; U is (N_d, nvec) real.  Returns (chi0 U, iters[, x, coeff])."""
     U = np.asarray(U, dtype=np.float64)
     if U.ndim == 1:
@@ -57,7 +57,7 @@ def chi0_apply(U, vloc, psi, eps, omega, shape, h, tol, max_iter,
     out = np.zeros((Nd, nvec))
 
     def applyH(v):
-        return fd.hamiltonian_apply(v, vloc, shape, h)
+        return fd.hamiltonian_apply(v, vloc, shape, h, bc=bc)
 
     for s0 in range(0, S, chunk):
         s1 = min(S, s0 + chunk)
@@ -74,9 +74,9 @@ def chi0_apply(U, vloc, psi, eps, omega, shape, h, tol, max_iter,
     return out, iters, status
 
 
-def chi0_sum_over_states(vloc, shape, h, n_occ, omega):
+def chi0_sum_over_states(vloc, shape, h, n_occ, omega, bc="periodic"):
     """Dense chi0(i omega) from Eq. 2 with every eigenpair of the dense H (tiny grids)."""
-    H = fd.hamiltonian_dense(vloc, shape, h)
+    H = fd.hamiltonian_dense(vloc, shape, h, bc=bc)
     dV = h ** 3
     evals, evecs = np.linalg.eigh(H)
     psi = evecs / np.sqrt(dV)                       # grid normalisation
@@ -96,13 +96,13 @@ def chi0_sum_over_states(vloc, shape, h, n_occ, omega):
     return chi
 
 
-def chi0_apply_unprojected_dense(U, vloc, psi, eps, omega, shape, h):
+def chi0_apply_unprojected_dense(U, vloc, psi, eps, omega, shape, h, bc="periodic"):
     """The paper's literal form at tiny size: unprojected right-hand side -psi_n u (Eq. 9),
     solved exactly by a dense complex solve, then Delta rho = 4 sum_n Re(psi_n x_n) (Eq. 8)."""
     U = np.asarray(U, dtype=np.float64)
     if U.ndim == 1:
         U = U[:, None]
-    H = fd.hamiltonian_dense(vloc, shape, h)
+    H = fd.hamiltonian_dense(vloc, shape, h, bc=bc)
     Nd, Ns = psi.shape
     out = np.zeros((Nd, U.shape[1]))
     for n in range(Ns):
@@ -112,11 +112,11 @@ def chi0_apply_unprojected_dense(U, vloc, psi, eps, omega, shape, h):
     return out
 
 
-def chi0_dense_projected(vloc, psi, eps, omega, shape, h):
+def chi0_dense_projected(vloc, psi, eps, omega, shape, h, bc="periodic"):
     """Dense chi0 of the projected-right-hand-side form, as a function of V_loc with Psi, eps fixed:
         chi0 = -4 sum_n D_n Re[A_n^{-1}] (I - P) D_n,  A_n = H - eps_n - i omega,  P = dV Psi Psi^T.
     At exact eigenpairs this equals the sum-over-states chi0 (tiny grids)."""
-    H = fd.hamiltonian_dense(vloc, shape, h)
+    H = fd.hamiltonian_dense(vloc, shape, h, bc=bc)
     Nd, Ns = psi.shape
     dV = h ** 3
     Q = np.eye(Nd) - dV * psi @ psi.T

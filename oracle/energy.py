@@ -15,16 +15,16 @@ from . import coulomb
 from .subspace import chol_orthonormalize, subspace_iteration
 
 
-def chi0_tilde_apply(V, vloc, psi, eps, omega, shape, h, tol, max_iter):
+def chi0_tilde_apply(V, vloc, psi, eps, omega, shape, h, tol, max_iter, bc="periodic"):
     """R = nu^{1/2} chi0(i omega) nu^{1/2} V (Algorithm 1, loop over trial vectors)."""
-    U = coulomb.nu_apply(V, shape, h, power=1)
-    D, iters, status = _chi0.chi0_apply(U, vloc, psi, eps, omega, shape, h, tol, max_iter)
-    R = coulomb.nu_apply(D, shape, h, power=1)
+    U = coulomb.nu_apply(V, shape, h, power=1, bc=bc)
+    D, iters, status = _chi0.chi0_apply(U, vloc, psi, eps, omega, shape, h, tol, max_iter, bc=bc)
+    R = coulomb.nu_apply(D, shape, h, power=1, bc=bc)
     return R, dict(iters=iters, status=status)
 
 
 def rpa_energy(vloc, psi, eps, shape, h, V0, omegas, weights, cocg_tol, cocg_max_iter,
-               subspace_iters, ec_tol=0.0, mode="warm", sq_order=0):
+               subspace_iters, ec_tol=0.0, mode="warm", sq_order=0, bc="periodic"):
     """Full E_c.  subspace_iters is the fixed count (ec_tol <= 0) or the cap (ec_tol > 0);
     it may be a scalar or one value per frequency.  Returns a dict with E_c, per-frequency
     energies, iteration counts, and the saved (V_m, C_m) per frequency."""
@@ -40,7 +40,7 @@ def rpa_energy(vloc, psi, eps, shape, h, V0, omegas, weights, cocg_tol, cocg_max
         om = float(omegas[m])
 
         def apply(Vb, om=om):
-            return chi0_tilde_apply(Vb, vloc, psi, eps, om, shape, h, cocg_tol, cocg_max_iter)
+            return chi0_tilde_apply(Vb, vloc, psi, eps, om, shape, h, cocg_tol, cocg_max_iter, bc)
 
         out = subspace_iteration(apply, V, float(weights[m]), int(its[m]), ec_tol, sq_order)
         res["E_freq"][m] = out["E"]

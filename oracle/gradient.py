@@ -25,16 +25,16 @@ from .subspace import g_prime
 
 
 def energy_backward(vloc, psi, eps, shape, h, omegas, weights, V_saved, C_saved,
-                    cocg_tol, cocg_max_iter):
+                    cocg_tol, cocg_max_iter, bc="periodic"):
     """dE_c/dV_loc (N_d,) by the adjoint formula, recomputing the Sternheimer solutions."""
     Nd, Ns = psi.shape
     grad = np.zeros(Nd)
     for m in range(len(omegas)):
         om = float(omegas[m])
         mu, Y = np.linalg.eigh(C_saved[m])
-        U = coulomb.nu_apply(V_saved[m] @ Y, shape, h, power=1)
+        U = coulomb.nu_apply(V_saved[m] @ Y, shape, h, power=1, bc=bc)
         _, _, _, X, coeff = _chi0.chi0_apply(U, vloc, psi, eps, om, shape, h, cocg_tol,
-                                             cocg_max_iter, return_solutions=True)
+                                             cocg_max_iter, return_solutions=True, bc=bc)
         nvec = U.shape[1]
         gp = g_prime(mu)
         for s in range(Ns * nvec):
@@ -46,18 +46,19 @@ def energy_backward(vloc, psi, eps, shape, h, omegas, weights, V_saved, C_saved,
     return grad
 
 
-def energy_backward_dense(vloc, psi, eps, shape, h, omegas, weights, V_saved, C_saved):
+def energy_backward_dense(vloc, psi, eps, shape, h, omegas, weights, V_saved, C_saved,
+                          bc="periodic"):
     """Same derivative from dense inverses (tiny grids): 4 sum_n Re[(A^{-1} b)_r (A^{-1}(I-P) b)_r],
     with no use of the eigenpair identity behind o_n."""
     Nd, Ns = psi.shape
     dV = h ** 3
-    H = fd.hamiltonian_dense(vloc, shape, h)
+    H = fd.hamiltonian_dense(vloc, shape, h, bc=bc)
     Q = np.eye(Nd) - dV * psi @ psi.T
     grad = np.zeros(Nd)
     for m in range(len(omegas)):
         om = float(omegas[m])
         mu, Y = np.linalg.eigh(C_saved[m])
-        U = coulomb.nu_apply(V_saved[m] @ Y, shape, h, power=1)
+        U = coulomb.nu_apply(V_saved[m] @ Y, shape, h, power=1, bc=bc)
         gp = g_prime(mu)
         for n in range(Ns):
             Ainv = np.linalg.inv(H - (eps[n] + 1j * om) * np.eye(Nd))

@@ -46,6 +46,7 @@ class Cell:
     residual: float       # max ||H psi - eps psi|| / ||psi|| from the generator
     seed: int
     meta: dict = field(default_factory=dict)
+    bc: str = "periodic"  # or "dirichlet": grid points at (i + 1) h, zero outside the box
 
     @property
     def nd(self):
@@ -93,16 +94,38 @@ def gaussian_wells(shape, h, centers, depths, sigmas):
     return V.reshape(-1)
 
 
+def gaussian_wells_box(shape, h, centers, depths, sigmas):
+    """Wells in an isolated box (no periodic images); grid point i at (i + 1) h."""
+    n0, n1, n2 = shape
+    x = (np.arange(n0) + 1) * h
+    y = (np.arange(n1) + 1) * h
+    z = (np.arange(n2) + 1) * h
+    V = np.zeros((n2, n1, n0))
+    for c, D, s in zip(centers, depths, sigmas):
+        ex = np.exp(-(x - c[0]) ** 2 / (2 * s * s))
+        ey = np.exp(-(y - c[1]) ** 2 / (2 * s * s))
+        ez = np.exp(-(z - c[2]) ** 2 / (2 * s * s))
+        V -= D * ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+    return V.reshape(-1)
+
+
 # ----------------------------------------------------------------------------- ground state
 
-def _fd_symbol(n, h):
-    """Fourier symbol of -D2 for the radius-6 centred formula, from the closed-form weights."""
+def _fd_w():
+    """Radius-6 centred second-derivative weights w_0 .. w_6 from their closed form."""
     from math import factorial
     M = FD_RADIUS
     w = np.zeros(M + 1)
     for p in range(1, M + 1):
         w[p] = 2.0 * (-1) ** (p + 1) * factorial(M) ** 2 / (p * p * factorial(M - p) * factorial(M + p))
     w[0] = -2.0 * w[1:].sum()
+    return w
+
+
+def _fd_symbol(n, h):
+    """Fourier symbol of -D2 for the radius-6 centred formula, from the closed-form weights."""
+    M = FD_RADIUS
+    w = _fd_w()
     th = 2.0 * np.pi * np.arange(n) / n
     s = -w[0] * np.ones(n)
     for p in range(1, M + 1):
@@ -159,6 +182,88 @@ def _chebyshev_filter(Hop, X, degree, a, b, a0):
         Ynew = (Hop(Y) - c * Y) * (2.0 * s_new / e) - (sigma * s_new) * X
         X, Y, sigma = Y, Ynew, s_new
     return Y
+
+
+class _BoxH:
+    """H = -1/2 Lap_h + V on an isolated box: the Dirichlet second difference along each axis
+    is the banded Toeplitz matrix of the stencil weights (reaches beyond the box read zero),
+    applied as a dense n x n matrix per axis."""
+
+    def __init__(self, shape, h, vloc):
+        from scipy.linalg import toeplitz
+        n0, n1, n2 = shape
+        self.shape = shape
+        w = _fd_w()
+
+        def T(n):
+            col = np.zeros(n)
+            col[:min(n, FD_RADIUS + 1)] = w[:min(n, FD_RADIUS + 1)]
+            return toeplitz(col) / (h * h)
+        self.Tx, self.Ty, self.Tz = T(n0), T(n1), T(n2)
+        self.v = vloc.reshape(n2, n1, n0)
+
+    def __call__(self, X):
+        n0, n1, n2 = self.shape
+        A = X.reshape(-1, n2, n1, n0)
+        L = (np.einsum("kzyx,wx->kzyw", A, self.Tx) + np.einsum("kzyx,wy->kzwx", A, self.Ty)
+             + np.einsum("kzyx,wz->kwyx", A, self.Tz))
+        return (-0.5 * L + self.v[None] * A).reshape(X.shape)
+
+    def upper_bound(self):
+        return float(2.0 * sum(np.abs(T).sum(axis=1).max() for T in (self.Tx, self.Ty, self.Tz))
+                     + self.v.max())
+
+    def dense(self):
+        n = int(np.prod(self.shape))
+        return self(np.eye(n))
+
+
+def box_ground_state(shape, h, vloc, n_states, seed, tol=1e-10, degree=24, max_outer=200):
+    """Lowest n_states eigenpairs of H on an isolated box (dense up to 4096 points, else the
+    Chebyshev-filtered subspace iteration of ground_state with the box operator)."""
+    Hop = _BoxH(shape, h, vloc)
+    nd = int(np.prod(shape))
+    if nd <= 4096:
+        H = Hop.dense()
+        H = 0.5 * (H + H.T)
+        ev, vec = dense_eigh(H, subset_by_index=[0, n_states - 1])
+        X = vec.T
+        return ev, X, np.linalg.norm(Hop(X) - ev[:, None] * X, axis=1)
+    rng = np.random.default_rng(seed + 7919)
+    m = n_states + max(8, n_states // 4)
+    X = rng.standard_normal((m, nd))
+    ev, X, HX = _rayleigh_ritz(Hop, X)
+    b = Hop.upper_bound()
+    for _ in range(max_outer):
+        X = _chebyshev_filter(Hop, X, degree, ev[-1], b, ev[0])
+        ev, X, HX = _rayleigh_ritz(Hop, X)
+        res = np.linalg.norm(HX - ev[:, None] * X, axis=1)
+        if res[:n_states + 1].max() <= tol:
+            break
+    return ev[:n_states + 1], X[:n_states + 1], res[:n_states + 1]
+
+
+def box_cell(shape, h, n_wells, n_occ, seed, tol=1e-10):
+    """A seeded isolated cell (Dirichlet boundary): Gaussian wells (D ~ U[1,3], sigma ~
+    U[0.8,1.2]) placed at least 3 sigma inside the box, lowest n_occ orbitals occupied; the
+    next seed is taken if the occupied/unoccupied gap is below 1e-3 Ha."""
+    L = np.array([(n + 1) * h for n in shape])
+    for s in range(seed, seed + 50):
+        rng = np.random.default_rng(s)
+        sig = rng.uniform(0.8, 1.2, n_wells)
+        dep = rng.uniform(1.0, 3.0, n_wells)
+        cen = 3.0 * sig[:, None] + rng.uniform(0, 1, (n_wells, 3)) * (L[None, :] - 6.0 * sig[:, None])
+        vloc = gaussian_wells_box(shape, h, cen, dep, sig)
+        ev, X, res = box_ground_state(shape, h, vloc, n_occ + 1, s, tol=tol)
+        if ev[n_occ] - ev[n_occ - 1] >= 1e-3:
+            psi = X[:n_occ] / np.sqrt(h ** 3)
+            idx = np.argmax(np.abs(psi), axis=1)
+            psi *= np.sign(psi[np.arange(n_occ), idx])[:, None]
+            return Cell(tuple(shape), float(h), vloc, np.ascontiguousarray(psi),
+                        ev[:n_occ].copy(), float(ev[n_occ]), float(res[:n_occ].max()), s,
+                        dict(seed_requested=seed, seed_used=s, n_wells=n_wells,
+                             gap=float(ev[n_occ] - ev[n_occ - 1])), bc="dirichlet")
+    raise RuntimeError("no seed with an occupied/unoccupied gap found")
 
 
 class _SpectralHTorch:
