@@ -62,6 +62,9 @@ extern "C" {
 #define RPA_INDEPENDENT   1   /* every frequency starts from V0; all frequencies still
                                  iterating share one batched chi0 launch per iteration */
 
+#define RPA_BC_PERIODIC   0   /* periodic cell */
+#define RPA_BC_DIRICHLET  1   /* isolated box (zero outside the grid) */
+
 /* Operation selectors for rpa_workspace_size(). */
 #define RPA_OP_COULOMB    0
 #define RPA_OP_CHI0       1
@@ -77,6 +80,9 @@ typedef struct rpa_cell {
     const double* v_loc;   /* device, N_d: local potential V_loc (Eq. 4 without V_xc, V_nl) */
     const double* psi;     /* device, N_d x N_s column-major, grid-normalised orbitals */
     const double* eps;     /* host, N_s orbital eigenvalues, strictly ascending */
+    int32_t bc;            /* RPA_BC_PERIODIC (0, the crystal cells) or RPA_BC_DIRICHLET (1:
+                              an isolated box, grid points at (i+1) h, every function zero
+                              outside; nu = 4 pi (-Lap_h)^{-1} without a null space) */
 } rpa_cell;
 
 /* Solver options.  rpa_default_options() fills the defaults noted below. */

@@ -26,6 +26,7 @@ class DeviceCell:
     vloc: torch.Tensor      # (N_d,) float64 device
     psi: torch.Tensor       # (N_s, N_d) float64 device
     eps: np.ndarray         # (N_s,) float64 host
+    bc: int = 0             # RPA_BC_PERIODIC or RPA_BC_DIRICHLET
 
     @property
     def nd(self):
@@ -44,6 +45,7 @@ class DeviceCell:
         c.psi = self.psi.data_ptr()
         self._eps_c = np.ascontiguousarray(self.eps, dtype=np.float64)
         c.eps = self._eps_c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        c.bc = int(self.bc)
         return c
 
 
@@ -54,7 +56,9 @@ def device_cell(cell, device="cuda"):
                                       device=device),
                       torch.as_tensor(np.ascontiguousarray(cell.psi), dtype=torch.float64,
                                       device=device),
-                      np.ascontiguousarray(cell.eps, dtype=np.float64))
+                      np.ascontiguousarray(cell.eps, dtype=np.float64),
+                      _L.RPA_BC_DIRICHLET if getattr(cell, "bc", "periodic") == "dirichlet"
+                      else _L.RPA_BC_PERIODIC)
 
 
 def _stream():
@@ -227,7 +231,8 @@ class RPAEnergy(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, vloc, cell, nr, omegas, weights, V0, opts=None):
-        dc = DeviceCell(cell.shape, cell.h, vloc.detach().contiguous(), cell.psi, cell.eps)
+        dc = DeviceCell(cell.shape, cell.h, vloc.detach().contiguous(), cell.psi, cell.eps,
+                        cell.bc)
         res = rpa_energy(dc, nr, omegas, weights, V0, opts, save=True)
         ctx.dc, ctx.omegas, ctx.weights, ctx.opts = dc, list(omegas), list(weights), opts
         ctx.save_for_backward(res["Vsave"][0], res["Csave"][0])

@@ -99,6 +99,8 @@ int check_geometry(const rpa_cell* c) {
     if (!(c->h > 0.0) || !std::isfinite(c->h)) return fail(RPA_EINVAL, "h must be finite and > 0");
     if (c->n_occ < 1 || c->n_occ > 128 || c->n_occ >= nd)
         return fail(RPA_EINVAL, "n_occ must be in [1, 128] and below N_d");
+    if (c->bc != RPA_BC_PERIODIC && c->bc != RPA_BC_DIRICHLET)
+        return fail(RPA_EINVAL, "bc must be RPA_BC_PERIODIC or RPA_BC_DIRICHLET");
     return RPA_OK;
 }
 
@@ -114,7 +116,7 @@ int check_cell(const rpa_cell* c) {
     return RPA_OK;
 }
 
-Grid grid_of(const rpa_cell* c) { return Grid{c->n[0], c->n[1], c->n[2], c->h}; }
+Grid grid_of(const rpa_cell* c) { return Grid{c->n[0], c->n[1], c->n[2], c->h, c->bc}; }
 
 int check_ws(void* ws, size_t ws_bytes, size_t need) {
     if (need == 0) return RPA_OK;
@@ -130,6 +132,7 @@ int check_ws(void* ws, size_t ws_bytes, size_t need) {
 // ------------------------------------------------------------------ buffer plans
 struct CoulombBuf {
     double *Ux, *Uy, *Uz, *kx, *ky, *kz, *tmp;
+    double* ework;   // isolated box: 1D eigenproblem work, 3 n^2
 };
 void carve_coulomb(Carver& cv, const Grid& g, int nvec, CoulombBuf& b) {
     b.Ux = cv.take<double>(size_t(g.n0) * g.n0);
@@ -139,6 +142,8 @@ void carve_coulomb(Carver& cv, const Grid& g, int nvec, CoulombBuf& b) {
     b.ky = cv.take<double>(g.n1);
     b.kz = cv.take<double>(g.n2);
     b.tmp = cv.take<double>(size_t(g.nd()) * nvec);
+    const size_t nm = size_t(std::max(g.n0, std::max(g.n1, g.n2)));
+    b.ework = g.periodic() ? nullptr : cv.take<double>(3 * nm * nm);
 }
 
 struct Chi0Buf {
@@ -308,9 +313,15 @@ void carve_back(Carver& cv, const Grid& g, int ns, int nr, const Opts& o, BackBu
 
 // ------------------------------------------------------------------ building blocks
 int coulomb_setup(const Grid& g, const CoulombBuf& b, hipStream_t s) {
-    RPA_HIP(launch_eigbasis_1d(g.n0, g.h, b.Ux, b.kx, s));
-    RPA_HIP(launch_eigbasis_1d(g.n1, g.h, b.Uy, b.ky, s));
-    RPA_HIP(launch_eigbasis_1d(g.n2, g.h, b.Uz, b.kz, s));
+    if (g.periodic()) {
+        RPA_HIP(launch_eigbasis_1d(g.n0, g.h, b.Ux, b.kx, s));
+        RPA_HIP(launch_eigbasis_1d(g.n1, g.h, b.Uy, b.ky, s));
+        RPA_HIP(launch_eigbasis_1d(g.n2, g.h, b.Uz, b.kz, s));
+    } else {
+        RPA_HIP(launch_eigbasis_1d_box(g.n0, g.h, b.Ux, b.kx, b.ework, s));
+        RPA_HIP(launch_eigbasis_1d_box(g.n1, g.h, b.Uy, b.ky, b.ework, s));
+        RPA_HIP(launch_eigbasis_1d_box(g.n2, g.h, b.Uz, b.kz, b.ework, s));
+    }
     return RPA_OK;
 }
 

@@ -176,6 +176,7 @@ hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     if (!ch.fn) return hipErrorInvalidConfiguration;
     a.nbuf = ch.nbuf;
     a.rs = lds_row(L.g.n0);
+    a.periodic = L.g.periodic() ? 1 : 0;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ch.fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(ch.lds));
     if (e != hipSuccess) return e;

@@ -65,6 +65,7 @@ struct Args {
     int* refinements;      // mixed: per system
     int nbuf;              // LDS plane buffers (2: one barrier per step, 1: two barriers)
     int rs;                // LDS row stride in entries: n0 + 12 rounded up to a multiple of 8
+    int periodic;          // 1: periodic cell; 0: isolated box (zero beyond the grid)
 };
 
 // Element access through a uniform base pointer and a 32-bit unsigned offset, so loads and
@@ -139,10 +140,13 @@ struct Cols {
 // Ghost rows carry only the real columns (the stencil has no diagonal terms).
 __device__ __forceinline__ int lds_center(int rs, int cx, int cy) { return (cy + 6) * rs + cx + 6; }
 
+// Isolated box: the ghost entries stay at the zeros written at kernel start.
 template <typename Q2>
-__device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int n1, int cx, int cy, Q2 v) {
+__device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int n1, int cx, int cy, Q2 v,
+                                            bool periodic) {
     const int c0 = lds_center(rs, cx, cy);
     L[c0] = v;
+    if (!periodic) return;
     if (cx < 6) L[c0 + n0] = v;
     if (cx >= n0 - 6) L[c0 - n0] = v;
     if (cy < 6) L[c0 + n1 * rs] = v;
@@ -195,11 +199,12 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
     for (int w = 0; w < (warm ? 0 : 12 / Z); ++w) {
 #pragma unroll
         for (int zz = 0; zz < Z; ++zz) {
-            int z = w * Z + zz - 6;
-            z += (z < 0) ? n2 : 0;
+            const int zu = w * Z + zz - 6;
+            const int z = zu + ((zu < 0) ? n2 : 0);
+            const bool in = a.periodic || zu >= 0;      // box: planes below 0 are zero
 #pragma unroll
             for (int i = 0; i < C; ++i)
-                Q[12 + zz][i] = cl.valid[i] ? lead.make(lead.load(z, i, true)) : Q2{0, 0};
+                Q[12 + zz][i] = (cl.valid[i] && in) ? lead.make(lead.load(z, i, true)) : Q2{0, 0};
         }
 #pragma unroll
         for (int s = 0; s < 12; ++s)
@@ -228,10 +233,12 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
             for (int zz = 0; zz < Z; ++zz) {
                 const int zu = zo + 6 + zz;
                 const int z = zu - ((zu >= n2) ? n2 : 0);
+                const bool in = a.periodic || zu < n2;      // box: planes beyond n2-1 are zero
 #pragma unroll
                 for (int i = 0; i < C; ++i)
                     if (cl.valid[i]) {
-                        LB[zz][i] = lead.load(z, i, zu < n2 || zu - n2 >= zo);
+                        LB[zz][i] = in ? lead.load(z, i, zu < n2 || zu - n2 >= zo)
+                                       : typename Lead::Buf{};
                         CB[zz][i] = cent.load(zo + zz, i);
                     }
             }
@@ -248,12 +255,14 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
             for (int zz = 0; zz < Z; ++zz) {
                 const int zu = zo + Z + 6 + zz;          // < 2 n2 since n2 >= 12, Z <= 4
                 const int z = zu - ((zu >= n2) ? n2 : 0);
+                const bool in = a.periodic || zu < n2;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     if (cl.valid[i]) {
                         // planes below zo have had their centre step; this step's
                         // centres run after these loads are issued
-                        LB[zz][i] = lead.load(z, i, zu < n2 || zu - n2 >= zo);
+                        LB[zz][i] = in ? lead.load(z, i, zu < n2 || zu - n2 >= zo)
+                                       : typename Lead::Buf{};
                         CB[zz][i] = cent.load(zo + Z + zz, i);
                     }
                 }
@@ -266,7 +275,8 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
 #pragma unroll
             for (int i = 0; i < C; ++i)
                 if (cl.valid[i])
-                    stage_point(L + zz * PL, a.rs, a.n0, a.n1, cl.cx[i], cl.cy[i], Q[6 + zz][i]);
+                    stage_point(L + zz * PL, a.rs, a.n0, a.n1, cl.cx[i], cl.cy[i], Q[6 + zz][i],
+                                a.periodic != 0);
         lds_barrier();
 #pragma unroll
         for (int zz = 0; zz < Z; ++zz) {
@@ -473,6 +483,15 @@ void cocg_wg(Args a_in) {
         cl.cy[i] = cc / n0;
     }
 
+    if (!a.periodic) {
+        // isolated box: every ghost entry of the staged planes reads zero; stage_point never
+        // writes ghosts in this mode, so clearing the plane buffers once suffices
+        const int nent = a.nbuf * Z * (a.n1 + 12) * a.rs;
+        double2* pl = reinterpret_cast<double2*>(planes);
+        for (int e = tid; e < nent; e += BS) pl[e] = double2{0.0, 0.0};
+        lds_barrier();
+    }
+
     double rho_re = 0, rho_im = 0, bb = 0, beta_re = 0, beta_im = 0, rr_ref = 0;
     int it = 0, st = 0, nref = 0;
     bool xlo_zero = true, xhi_zero = true, done = false;
@@ -485,7 +504,10 @@ void cocg_wg(Args a_in) {
     while (!done) {
         const bool first = (it == 0);
         // ---------------------------------------------------------- sweep 1
-        if (!first && !cold) {
+        // (isolated box: the queue left by a sweep holds the planes past the top wall, not the
+        // planes below the bottom one, so every sweep starts cold)
+        const bool carry = !first && !cold && a.periodic;
+        if (carry) {
             // warm start of sweep 1 from the queue: p_new = r + beta p on planes -6 .. 5,
             // four planes at a time
             const T br = T(beta_re), bi = T(beta_im);
@@ -512,7 +534,7 @@ void cocg_wg(Args a_in) {
         }
         LeadPnew<T2, C> l1{r, pa, P, cl.col, first, beta_re, beta_im};
         CentSigma<T2, C> c1{pb, P, cl.col, first, {0, 0, 0, 0, 0, 0, 0}};
-        march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q, !first && !cold);
+        march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q, carry);
         cold = false;
         wg_reduce<7>(c1.acc, red);
         if (first) {
@@ -541,13 +563,15 @@ void cocg_wg(Args a_in) {
             if constexpr (MIXED) {
                 CentUpdate<T2, float2> c2{r, reinterpret_cast<float2*>(a.xlo) + off, P, cl.col,
                                           xlo_zero, alpha_re, alpha_im, {0, 0, 0}};
-                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q, true);
+                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q,
+                                   a.periodic != 0);
                 wg_reduce<3>(c2.acc, red);
                 acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
             } else {
                 CentUpdate<T2, XS> c2{r, reinterpret_cast<XS*>(a.x) + off, P, cl.col, first,
                                       alpha_re, alpha_im, {0, 0, 0}};
-                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q, true);
+                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q,
+                                   a.periodic != 0);
                 wg_reduce<3>(c2.acc, red);
                 acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
             }

@@ -258,15 +258,17 @@ struct StoreZ {  // Y[xy + P (c + n2 j)]
     }
 };
 
+// s^power = (4 pi / (kx + ky + kz))^{power/2} per mode; zero_mode: the all-zero-index mode (the
+// constant of a periodic grid) is the null space and gets 0.
 __global__ void kron_scale(double* X, int n0, int n1, int n2, int64_t total, const double* kx,
-                           const double* ky, const double* kz, int power) {
+                           const double* ky, const double* kz, int power, int zero_mode) {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= total) return;
     const int64_t nd = int64_t(n0) * n1 * n2;
     const int64_t p = i % nd;
     const int x = int(p % n0), y = int((p / n0) % n1), z = int(p / (int64_t(n0) * n1));
     double s = 0.0;
-    if (x != 0 || y != 0 || z != 0) {
+    if (!zero_mode || x != 0 || y != 0 || z != 0) {
         const double K = kx[x] + ky[y] + kz[z];
         s = (power == 2) ? 4.0 * M_PI / K : sqrt(4.0 * M_PI / K);
     }
@@ -363,6 +365,26 @@ hipError_t launch_eigbasis_1d(int n, double h, double* U, double* kappa, hipStre
     return hipGetLastError();
 }
 
+// A = -D2 of an isolated box: A[i + n j] = -w_|i-j| / h^2 for |i - j| <= 6 (reaches beyond the
+// walls dropped)
+__global__ void box_matrix_kernel(int n, double h, W7 wt, double* A) {
+    const int j = blockIdx.x, i = threadIdx.x;
+    if (i >= n) return;
+    const int d = i > j ? i - j : j - i;
+    A[i + int64_t(n) * j] = (d <= 6) ? -wt.w[d] / (h * h) : 0.0;
+}
+
+hipError_t launch_eigbasis_1d_box(int n, double h, double* U, double* kappa, double* work,
+                                  hipStream_t s) {
+    W7 wt;
+    fd_weights(wt.w);
+    double* A = work;
+    hipLaunchKernelGGL(box_matrix_kernel, dim3(n), dim3((n + 63) / 64 * 64), 0, s, n, h, wt, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_syevj(n, A, work + int64_t(n) * n, kappa, U, s);
+}
+
 static hipError_t kron_chunk(const Grid& g, int power, int nvec, const double* in, double* out,
                              double* tmp, const double* Ux, const double* Uy, const double* Uz,
                              const double* kx, const double* ky, const double* kz,
@@ -383,7 +405,7 @@ static hipError_t kron_chunk(const Grid& g, int power, int nvec, const double* i
     if (e != hipSuccess) return e;
     const int64_t total = g.nd() * nvec;
     hipLaunchKernelGGL(kron_scale, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, tmp, n0,
-                       n1, n2, total, kx, ky, kz, power);
+                       n1, n2, total, kx, ky, kz, power, g.periodic() ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // inverse z, y, x

@@ -54,7 +54,9 @@ struct Carver {
 struct Grid {
     int n0, n1, n2;
     double h;
+    int bc = 0;      // RPA_BC_PERIODIC or RPA_BC_DIRICHLET
     int64_t nd() const { return int64_t(n0) * n1 * n2; }
+    bool periodic() const { return bc == 0; }
 };
 
 // 12th-order centred second-derivative weights w_0..w_6 (exact rationals, see fd_weights()).
@@ -65,6 +67,10 @@ void fd_weights(double w[7]);
 
 // Kronecker nu^{power/2}: 1D eigenbases (basis[3] device, n_a*n_a each, kappa[3] device n_a)
 hipError_t launch_eigbasis_1d(int n, double h, double* U, double* kappa, hipStream_t s);
+// Isolated box: eigenpairs of the Dirichlet -D2 (banded Toeplitz of the weights, n <= 4096
+// not required small but work >= 3 n^2 doubles), kappa ascending, U[t + n a] = mode a.
+hipError_t launch_eigbasis_1d_box(int n, double h, double* U, double* kappa, double* work,
+                                  hipStream_t s);
 hipError_t launch_kron_apply(const Grid& g, int power, int nvec, const double* in, double* out,
                              double* tmp, const double* Ux, const double* Uy, const double* Uz,
                              const double* kx, const double* ky, const double* kz,

@@ -14,12 +14,14 @@ RPA_OK, RPA_ENOTCONV = 0, 1
 RPA_EINVAL, RPA_EWORKSPACE, RPA_EBREAKDOWN, RPA_ENOTPD, RPA_EHIP, RPA_ENOTIMPL = -1, -2, -3, -4, -5, -6
 RPA_FP64, RPA_MIXED = 0, 1
 RPA_WARM, RPA_INDEPENDENT = 0, 1
+RPA_BC_PERIODIC, RPA_BC_DIRICHLET = 0, 1
 RPA_OP_COULOMB, RPA_OP_CHI0, RPA_OP_SUBSPACE, RPA_OP_ENERGY, RPA_OP_BACKWARD = 0, 1, 2, 3, 4
 
 
 class RpaCell(ctypes.Structure):
     _fields_ = [("n", c_int32 * 3), ("n_occ", c_int32), ("h", c_double),
-                ("v_loc", c_void_p), ("psi", c_void_p), ("eps", POINTER(c_double))]
+                ("v_loc", c_void_p), ("psi", c_void_p), ("eps", POINTER(c_double)),
+                ("bc", c_int32)]
 
 
 class RpaOptions(ctypes.Structure):

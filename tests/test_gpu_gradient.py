@@ -21,7 +21,7 @@ def say(*a):
 
 
 def frozen_energy(dc, vloc, om, W, Vm, tol):
-    cell = api.DeviceCell(dc.shape, dc.h, vloc, dc.psi, dc.eps)
+    cell = api.DeviceCell(dc.shape, dc.h, vloc, dc.psi, dc.eps, dc.bc)
     r = api.rpa_subspace_iter(cell, om, W, Vm.clone(), dict(cocg_tol=tol, subspace_iters=1,
                                                              ec_tol=0.0), want_ritz=False,
                               want_saved=False)
