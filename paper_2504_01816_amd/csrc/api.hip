@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -344,6 +345,13 @@ struct CocgTimer {
     int device = -1;
 };
 static thread_local CocgTimer g_timer;
+
+// Destroy this thread's timing events (cell worker threads, before they end).
+void release_timer() {
+    if (g_timer.start) (void)hipEventDestroy(g_timer.start);
+    if (g_timer.stop) (void)hipEventDestroy(g_timer.stop);
+    g_timer = CocgTimer{};
+}
 
 int timer_events(hipEvent_t* a, hipEvent_t* b) {
     int dev = 0;
@@ -695,6 +703,130 @@ int energy_batched(const rpa_cell* cell, int nr, int nfreq, const double* omega,
     return RPA_OK;
 }
 
+
+// ------------------------------------------------------------------ multi-cell energy
+size_t energy_cell_bytes(const Grid& g, int ns, int nr, int nfreq, const Opts& o) {
+    Carver dry;
+    if (o.freq_mode == RPA_INDEPENDENT) {
+        BatchBuf b;
+        carve_batch(dry, g, ns, nr, nfreq, o, b);
+    } else {
+        EnergyBuf b;
+        carve_energy(dry, g, ns, nr, o, b);
+    }
+    return (dry.used + 255) / 256 * 256;
+}
+
+// One cell's share of rpa_energy: inputs, its workspace slice, and its results.
+struct CellRun {
+    const rpa_cell* cell = nullptr;
+    int nr = 0;
+    const double* V0 = nullptr;
+    double* Vsave = nullptr;
+    double* Csave = nullptr;
+    char* ws = nullptr;
+    SolveTally t;
+    int applies = 0;
+    double ec = 0.0;
+    std::vector<double> ecf;
+    std::vector<int> its;
+    int rc = RPA_OK;
+    std::string err;
+};
+
+// E_c of one cell on stream s (warm: frequencies in sequence; independent: batched).
+int energy_cell(CellRun& r, int nfreq, const double* omega, const double* weight, const Opts& o,
+                hipStream_t s) {
+    const rpa_cell* cell = r.cell;
+    const Grid g = grid_of(cell);
+    const int64_t nd = g.nd();
+    const int m_r = r.nr;
+    rpa_stats st{};
+    Carver cv{r.ws, 0};
+    int rc = RPA_OK;
+    if (o.freq_mode == RPA_INDEPENDENT) {
+        BatchBuf b;
+        carve_batch(cv, g, cell->n_occ, m_r, nfreq, o, b);
+        rc = energy_batched(cell, m_r, nfreq, omega, weight, r.V0, r.Vsave, r.Csave, o, b, r.t,
+                            &st, &r.ec, r.ecf.data(), r.its.data(), s);
+    } else {
+        EnergyBuf b;
+        carve_energy(cv, g, cell->n_occ, m_r, o, b);
+        rc = coulomb_setup(g, b.sb.cb, s);
+        if (rc >= 0) rc = chol_orthonormalize(g, m_r, r.V0, b.Vstart, b.sb, s);
+        if (rc >= 0 && hipSuccess != launch_copy(nd * m_r, b.Vstart, b.Vcur, s))
+            rc = fail(RPA_EHIP, "copy launch failed");
+        double total = 0.0;
+        for (int m = 0; m < nfreq && rc >= 0; ++m) {
+            double* vs = r.Vsave ? r.Vsave + size_t(m) * nd * m_r : nullptr;
+            double* csv = r.Csave ? r.Csave + size_t(m) * m_r * m_r : nullptr;
+            SubResult res;
+            rc = subspace_iter(cell, g, omega[m], weight[m], m_r, b.Vcur, vs, csv, nullptr, o,
+                               b.sb, r.t, &st, res, s, true);
+            if (rc < 0) break;
+            total += res.E;
+            r.ecf[m] = res.E;
+            r.its[m] = res.n_iter;
+        }
+        r.ec = total;
+    }
+    r.applies = st.chi0_applies;
+    r.rc = rc;
+    if (rc < 0) r.err = g_last_error;
+    return rc;
+}
+
+// Several cells at once: one host thread and one stream per cell (default priority), each
+// started after the work already queued on the caller's stream, which then waits for all of
+// them.  Cells are independent, so the results equal those of the one-cell calls; the GPU is
+// shared by the cells' launches instead of running them one after another.
+int energy_cells_concurrent(std::vector<CellRun>& run, int nfreq, const double* omega,
+                            const double* weight, const Opts& o, hipStream_t s) {
+    int dev = 0;
+    RPA_HIP(hipGetDevice(&dev));
+    hipEvent_t ready;
+    RPA_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    RPA_HIP(hipEventRecord(ready, s));
+    const int n = int(run.size());
+    std::vector<hipStream_t> st(n, nullptr);
+    std::vector<hipEvent_t> done(n, nullptr);
+    for (int c = 0; c < n; ++c) {
+        RPA_HIP(hipStreamCreateWithFlags(&st[c], hipStreamNonBlocking));
+        RPA_HIP(hipEventCreateWithFlags(&done[c], hipEventDisableTiming));
+        RPA_HIP(hipStreamWaitEvent(st[c], ready, 0));
+    }
+    std::vector<std::thread> th;
+    for (int c = 0; c < n; ++c) {
+        th.emplace_back([&, c] {
+            if (hipSetDevice(dev) != hipSuccess) {
+                run[c].rc = RPA_EHIP;
+                run[c].err = "hipSetDevice failed in a cell worker";
+                return;
+            }
+            energy_cell(run[c], nfreq, omega, weight, o, st[c]);
+            (void)hipEventRecord(done[c], st[c]);
+            (void)hipStreamSynchronize(st[c]);
+            release_timer();
+        });
+    }
+    for (auto& t : th) t.join();
+    int rc = RPA_OK;
+    for (int c = 0; c < n; ++c) {
+        (void)hipStreamWaitEvent(s, done[c], 0);
+        if (run[c].rc < 0 && rc >= 0) {
+            rc = run[c].rc;
+            set_error("cell " + std::to_string(c) + ": " + run[c].err);
+        }
+    }
+    RPA_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < n; ++c) {
+        (void)hipEventDestroy(done[c]);
+        (void)hipStreamDestroy(st[c]);
+    }
+    (void)hipEventDestroy(ready);
+    return rc;
+}
+
 }  // namespace
 }  // namespace rpa
 
@@ -757,13 +889,11 @@ int rpa_workspace_size(int32_t op, int32_t ncell, const rpa_cell* cells, const i
             case RPA_OP_CHI0: { Chi0Buf b; carve_chi0(cv, g, ns, nvec[c], o, false, false, b); break; }
             case RPA_OP_SUBSPACE: { SubBuf b; carve_sub(cv, g, ns, nvec[c], o, b); break; }
             case RPA_OP_ENERGY: {
-                if (o.freq_mode == RPA_INDEPENDENT) {
-                    if (nfreq < 1) return fail(RPA_EINVAL, "nfreq must be >= 1");
-                    BatchBuf b; carve_batch(cv, g, ns, nvec[c], nfreq, o, b);
-                } else {
-                    EnergyBuf b; carve_energy(cv, g, ns, nvec[c], o, b);
-                }
-                break;
+                if (o.freq_mode == RPA_INDEPENDENT && nfreq < 1)
+                    return fail(RPA_EINVAL, "nfreq must be >= 1");
+                // cells run concurrently, each in its own slice: the sizes add up
+                need += energy_cell_bytes(g, ns, nvec[c], std::max(1, int(nfreq)), o);
+                continue;
             }
             case RPA_OP_BACKWARD: {
                 if (nfreq < 1) return fail(RPA_EINVAL, "nfreq must be >= 1");
@@ -871,75 +1001,60 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
     }
     Opts o;
     RPA_CHECK(read_opts(opt, &o));
-    size_t need = 0;
+    // each cell works in its own slice of the workspace (256-byte aligned offsets)
+    std::vector<size_t> offs(ncell + 1, 0);
     for (int c = 0; c < ncell; ++c) {
         RPA_CHECK(check_cell(&cells[c]));
         const Grid g = grid_of(&cells[c]);
         if (nr[c] < 1 || nr[c] > 4096 || nr[c] > g.nd())
             return fail(RPA_EINVAL, "nr must be in [1, min(4096, N_d)]");
         if (!V0[c]) return fail(RPA_EINVAL, "V0 pointer is NULL");
-        Carver dry;
-        if (o.freq_mode == RPA_INDEPENDENT) {
-            BatchBuf b;
-            carve_batch(dry, g, cells[c].n_occ, nr[c], nfreq, o, b);
-        } else {
-            EnergyBuf b;
-            carve_energy(dry, g, cells[c].n_occ, nr[c], o, b);
-        }
-        need = std::max(need, dry.used);
+        offs[c + 1] = offs[c] + energy_cell_bytes(g, cells[c].n_occ, nr[c], nfreq, o);
     }
-    RPA_CHECK(check_ws(ws, ws_bytes, need));
+    RPA_CHECK(check_ws(ws, ws_bytes, offs[ncell]));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    SolveTally t;
-    if (o.freq_mode == RPA_INDEPENDENT) {
-        for (int c = 0; c < ncell; ++c) {
-            const rpa_cell* cell = &cells[c];
-            const Grid g = grid_of(cell);
-            Carver cv{static_cast<char*>(ws), 0};
-            BatchBuf b;
-            carve_batch(cv, g, cell->n_occ, nr[c], nfreq, o, b);
-            int rc = energy_batched(cell, nr[c], nfreq, omega, weight, V0[c],
-                                    (Vsave && Vsave[c]) ? Vsave[c] : nullptr,
-                                    (Csave && Csave[c]) ? Csave[c] : nullptr, o, b, t, stats,
-                                    &ec_out[c], ec_freq_out ? ec_freq_out + size_t(c) * nfreq : nullptr,
-                                    iters_out ? iters_out + size_t(c) * nfreq : nullptr, s);
-            if (rc < 0) {
-                add_stats(stats, t);
-                return rc;
-            }
-        }
-        add_stats(stats, t);
-        return solve_status(t);
-    }
+    std::vector<CellRun> run(ncell);
     for (int c = 0; c < ncell; ++c) {
-        const rpa_cell* cell = &cells[c];
-        const Grid g = grid_of(cell);
-        const int64_t nd = g.nd();
-        const int m_r = nr[c];
-        Carver cv{static_cast<char*>(ws), 0};
-        EnergyBuf b;
-        carve_energy(cv, g, cell->n_occ, m_r, o, b);
-        RPA_CHECK(coulomb_setup(g, b.sb.cb, s));
-        RPA_CHECK(chol_orthonormalize(g, m_r, V0[c], b.Vstart, b.sb, s));
-        RPA_HIP(launch_copy(nd * m_r, b.Vstart, b.Vcur, s));
-        double total = 0.0;
-        for (int m = 0; m < nfreq; ++m) {
-            double* vs = (Vsave && Vsave[c]) ? Vsave[c] + size_t(m) * nd * m_r : nullptr;
-            double* csv = (Csave && Csave[c]) ? Csave[c] + size_t(m) * m_r * m_r : nullptr;
-            SubResult res;
-            int rc = subspace_iter(cell, g, omega[m], weight[m], m_r, b.Vcur, vs, csv, nullptr, o,
-                                   b.sb, t, stats, res, s, true);
-            if (rc < 0) {
-                add_stats(stats, t);
-                return rc;
-            }
-            total += res.E;
-            if (ec_freq_out) ec_freq_out[size_t(c) * nfreq + m] = res.E;
-            if (iters_out) iters_out[size_t(c) * nfreq + m] = res.n_iter;
+        CellRun& r = run[c];
+        r.cell = &cells[c];
+        r.nr = nr[c];
+        r.V0 = V0[c];
+        r.Vsave = (Vsave && Vsave[c]) ? Vsave[c] : nullptr;
+        r.Csave = (Csave && Csave[c]) ? Csave[c] : nullptr;
+        r.ws = static_cast<char*>(ws) + offs[c];
+        r.ecf.assign(nfreq, 0.0);
+        r.its.assign(nfreq, 0);
+    }
+    int rc;
+    if (ncell == 1) {
+        rc = energy_cell(run[0], nfreq, omega, weight, o, s);
+    } else {
+        rc = energy_cells_concurrent(run, nfreq, omega, weight, o, s);
+    }
+    SolveTally t;
+    for (int c = 0; c < ncell; ++c) {
+        const CellRun& r = run[c];
+        t.iters_total += r.t.iters_total;
+        t.systems += r.t.systems;
+        t.launches += r.t.launches;
+        t.refinements += r.t.refinements;
+        t.iters_max = std::max(t.iters_max, r.t.iters_max);
+        t.unconv += r.t.unconv;
+        t.breakdown += r.t.breakdown;
+        t.kernel_ms += r.t.kernel_ms;
+        t.point_iters += r.t.point_iters;
+        if (stats) {
+            stats->chi0_applies += r.applies;
+            stats->subspace_iters_total += r.applies;
         }
-        ec_out[c] = total;
+        ec_out[c] = r.ec;
+        for (int m = 0; m < nfreq; ++m) {
+            if (ec_freq_out) ec_freq_out[size_t(c) * nfreq + m] = r.ecf[m];
+            if (iters_out) iters_out[size_t(c) * nfreq + m] = r.its[m];
+        }
     }
     add_stats(stats, t);
+    if (rc < 0) return rc;
     return solve_status(t);
 }
 

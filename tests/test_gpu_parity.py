@@ -331,3 +331,26 @@ def test_batched_frequencies_with_sq_match_oracle(small3):
                          dict(cocg_tol=1e-11, subspace_iters=3, ec_tol=0.0, freq_mode=INDEPENDENT,
                               sq_order=2))
     np.testing.assert_allclose(res["E_freq"][0], ref["E_freq"], rtol=1e-9)
+
+
+# ---------------------------------------------------------------------------- several cells
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, MIXED)])
+def test_several_cells_run_concurrently_and_match_single_calls(mode, precision):
+    # uneven cells (one of them an isolated box) in one rpa_energy call run on their own
+    # streams at the same time; each cell's result equals its own one-cell call bitwise
+    say("three cells concurrently, mode", mode, "precision", precision)
+    cells = [synth.small_cell(n=12, h=0.5, n_wells=2, n_occ=3, seed=11),
+             synth.box_cell((12, 12, 13), 0.5, 2, 4, 21),
+             synth.small_cell(n=14, h=0.45, n_wells=3, n_occ=5, seed=12)]
+    nrs = [6, 8, 10]
+    om, W = synth.frequency_rule(3)
+    dcs = [api.device_cell(c, DEV) for c in cells]
+    V0s = [torch.tensor(np.random.default_rng(20 + i).standard_normal((r, c.nd)), device=DEV)
+           for i, (c, r) in enumerate(zip(cells, nrs))]
+    opts = dict(cocg_tol=1e-10, subspace_iters=3, ec_tol=0.0, freq_mode=mode, precision=precision)
+    res = api.rpa_energy(dcs, nrs, om, W, V0s, opts, save=True)
+    assert res["status"] == 0
+    for i in range(3):
+        one = api.rpa_energy(dcs[i], nrs[i], om, W, [V0s[i]], opts, save=True)
+        assert np.array_equal(one["E_freq"][0], res["E_freq"][i])
+        assert torch.equal(one["Csave"][0], res["Csave"][i])
