@@ -2,14 +2,18 @@
 
 A step is one pass of the whole hot path on the 24^3 workload (16 Gaussian wells,
 N_s = 16, N_r = 64, 8 Gauss-Legendre frequencies, COCG tol 1e-8): rpa_energy over all
-frequencies (subspace iteration from the highest frequency to the lowest, warm starts,
-stopping at a relative energy change of 1e-8, at most 50 iterations per frequency) and
-then rpa_energy_backward (one chi0 block-apply per frequency).  Inputs are synthetic,
+frequencies (subspace iteration stopping at a relative energy change of 1e-8, at most 50
+iterations per frequency) and then rpa_energy_backward (one chi0 block-apply per
+frequency).  By default the frequencies are batched (every frequency starts from V0 and all
+frequencies still iterating share one COCG launch per subspace iteration) in FP64;
+--freq-mode warm runs Algorithm 1's warm-started sequence instead.  Inputs are synthetic,
 seeded and resident in HBM before the timed region.
 
 Printed: one JSON line with the metric (chi0 block-applies per second over the timed
 steps), time-to-E_c, the roofline of the dominant kernel (batched COCG) measured with
-HIP events on its own stream, and the CPU oracle timed on a bounded sample.
+HIP events on its own stream, the same path with complex64 state and float64 reliable
+updates (one warm-up, one timed step: "compare"), and the CPU oracle timed on a bounded
+sample.
 """
 import argparse
 import json
@@ -34,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=1, help="workload index (0..4)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--freq-mode", default="warm", choices=["warm", "independent"],
+    ap.add_argument("--freq-mode", default="independent", choices=["warm", "independent"],
                     help="warm: frequencies in sequence, each started from the previous one's "
                          "subspace (Algorithm 1); independent: every frequency from V0, all "
                          "frequencies batched into one chi0 launch per subspace iteration")
@@ -44,9 +48,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ec-tol", type=float, default=1e-8)
     ap.add_argument("--max-subspace", type=int, default=50)
-    ap.add_argument("--compare", default="batched", choices=["none", "batched"],
-                    help="batched: after the timed steps, also time one step (after one warm-up) "
-                         "of the batched-frequency path in FP64 and in mixed precision")
+    ap.add_argument("--compare", default="other", choices=["none", "other"],
+                    help="other: after the timed steps, also time one step (after one warm-up) "
+                         "of the same path in the other precision")
     return ap.parse_args()
 
 
@@ -201,34 +205,29 @@ def main():
                      "alg_bytes_per_point_iter": ALG_BYTES[args.precision],
                      "cocg_share_of_step": cocg_ms * 1e-3 / T},
     }
-    if args.compare == "batched":
-        # the metric's comparison: the batched-frequency path (every frequency from V0, all of
-        # them in one COCG launch per subspace iteration) in FP64 and with complex64 state and
-        # float64 reliable updates, same inputs and stopping rule
-        comp = {}
-        e_ref = None
-        for name, prec_c in (("fp64_batched", L.RPA_FP64), ("mixed_batched", L.RPA_MIXED)):
-            o2 = dict(opts, precision=prec_c, freq_mode=L.RPA_INDEPENDENT)
-            step(o2)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            s2 = step(o2)
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t
-            ab = ALG_BYTES["fp64" if prec_c == L.RPA_FP64 else "mixed"]
-            comp[name] = {"chi0_block_applies_per_s": s2["applies"] / t,
-                          "time_to_ec_s": s2["fwd_s"], "backward_s": s2["bwd_s"],
-                          "E_c": s2["E"], "subspace_iters": s2["iters"],
-                          "cocg_alg_GBs": ab * s2["point_iters"] / (s2["cocg_ms"] * 1e-3) / 1e9}
-            if e_ref is None:
-                e_ref = s2["E"]
-            else:
-                comp[name]["E_c_rel_diff_vs_fp64_batched"] = [
-                    abs(a - b) / abs(b) for a, b in zip(s2["E"], e_ref)]
-            print("[bench] compare %s: %.2f s fwd, %.2f applies/s, E_c %s" % (
-                name, s2["fwd_s"], comp[name]["chi0_block_applies_per_s"], s2["E"]),
-                file=sys.stderr, flush=True)
-        out["compare"] = comp
+    if args.compare == "other":
+        # the metric's comparison: the same path and inputs in the other precision (complex64
+        # state with float64 reliable updates against complex128)
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        o2 = dict(opts, precision=L.RPA_MIXED if other == "mixed" else L.RPA_FP64)
+        step(o2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s2 = step(o2)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t
+        out["compare"] = {
+            "precision": other,
+            "chi0_block_applies_per_s": s2["applies"] / t,
+            "time_to_ec_s": s2["fwd_s"], "backward_s": s2["bwd_s"],
+            "E_c": s2["E"], "subspace_iters": s2["iters"],
+            "E_c_rel_diff": [abs(a - b) / abs(b) for a, b in zip(s2["E"], steps[-1]["E"])],
+            "cocg_alg_GBs": ALG_BYTES[other] * s2["point_iters"] / (s2["cocg_ms"] * 1e-3) / 1e9,
+            "time_to_ec_ratio_vs_main": s2["fwd_s"] / out["time_to_ec_s"],
+        }
+        print("[bench] compare %s: %.2f s fwd, %.2f applies/s, E_c %s" % (
+            other, s2["fwd_s"], out["compare"]["chi0_block_applies_per_s"], s2["E"]),
+            file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(wl)
