@@ -16,6 +16,11 @@
 //    The next step's planes are loaded before the current step computes, and the barrier
 //    only orders LDS (global loads and stores stay in flight): every global address is
 //    read and written by one thread only, so LDS is the sole cross-thread channel.
+//  * Large planes (whose whole-plane columns per thread would spill registers) are marched
+//    in row slabs, one after another, one column per thread: each slab's 6 rows above and
+//    below are read from memory for every centre plane (the vector they come from is not
+//    written in the same sweep), and each sweep ends with a workgroup-wide memory barrier,
+//    since the next sweep reads rows that other threads wrote.
 //  * Mixed precision (T = float): r, p and the partial solution x_lo are complex64; the
 //    solution x_hi and the residual r_hi are complex float64.  When the complex64 residual
 //    has dropped by refine_tol since the last update (or reaches the tolerance), a reliable
@@ -26,7 +31,8 @@
 //  * Reductions accumulate in float64 and are fixed-order: results are bitwise
 //    reproducible run to run.
 // Layout: state arrays are system-major, nsys x N_d, complex interleaved (re, im).
-// Constraints: n2 >= 12 and divisible by Z; n0, n1 >= 7.
+// Constraints: n2 >= 12 and divisible by Z; n0, n1 >= 7; slab mode: rows >= 12 and at
+// least 12 n0 threads.
 #pragma once
 
 #include <type_traits>
@@ -66,6 +72,8 @@ struct Args {
     int nbuf;              // LDS plane buffers (2: one barrier per step, 1: two barriers)
     int rs;                // LDS row stride in entries: n0 + 12 rounded up to a multiple of 8
     int periodic;          // 1: periodic cell; 0: isolated box (zero beyond the grid)
+    int nslab;             // row slabs a sweep marches one after another (1: whole plane)
+    int rows;              // rows per slab (n1 / nslab)
 };
 
 // Element access through a uniform base pointer and a 32-bit unsigned offset, so loads and
@@ -126,31 +134,54 @@ __device__ __forceinline__ void wg_reduce(double (&v)[NV], double* red) {
     lds_barrier();
 }
 
+// The columns (x, y) a thread owns in the current slab: thread t owns local columns
+// t, t + BS, ... of the slab's rows [y0, y0 + rows); col is the global column y n0 + x, cyl the
+// row inside the slab.
 template <int C>
 struct Cols {
-    int col[C], cx[C], cy[C];
+    int col[C], cx[C], cyl[C];
     bool valid[C];
+    int y0;
 };
 
-// LDS plane layout: n1 + 12 rows of RS >= n0 + 12 entries (RS a multiple of 8, so that a
-// wave's reads stay free of bank conflicts where it crosses a row end).  Row y + 6 holds
-// x = -6 .. n0+5 of grid row y, for y = -6 .. n1+5: the 6 ghost columns on each side and the
-// 6 ghost rows above and below hold the periodic images, so every neighbour of a point is a
-// fixed offset from it (+-k along x, +-k RS along y) and no wrap is computed in the stencil.
-// Ghost rows carry only the real columns (the stencil has no diagonal terms).
-__device__ __forceinline__ int lds_center(int rs, int cx, int cy) { return (cy + 6) * rs + cx + 6; }
+template <int C>
+__device__ __forceinline__ void make_cols(const Args& a, int slab, int tid, int BS, Cols<C>& cl) {
+    const int ps = a.rows * a.n0;
+    cl.y0 = slab * a.rows;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const int t = tid + i * BS;
+        cl.valid[i] = t < ps;
+        const int tt = cl.valid[i] ? t : 0;
+        cl.cx[i] = tt % a.n0;
+        cl.cyl[i] = tt / a.n0;
+        cl.col[i] = (cl.y0 + cl.cyl[i]) * a.n0 + cl.cx[i];
+    }
+}
 
-// Isolated box: the ghost entries stay at the zeros written at kernel start.
+// LDS plane layout: rows + 12 rows of RS >= n0 + 12 entries (RS a multiple of 8, so that a
+// wave's reads stay free of bank conflicts where it crosses a row end).  Row r + 6 holds
+// x = -6 .. n0+5 of slab row r, for r = -6 .. rows+5: the 6 ghost columns on each side hold
+// the periodic images along x, the 6 rows above and below the slab hold the neighbouring
+// rows (periodic images of the slab's own rows when the slab is the whole plane, rows of the
+// other slabs loaded from memory otherwise), so every neighbour of a point is a fixed offset
+// from it (+-k along x, +-k RS along y) and no wrap is computed in the stencil.  Rows outside
+// the slab carry only the real columns (the stencil has no diagonal terms).
+__device__ __forceinline__ int lds_center(int rs, int cx, int cyl) { return (cyl + 6) * rs + cx + 6; }
+
+// Isolated box: ghost entries that lie beyond the walls stay at the zeros written at kernel
+// start.  y ghosts are written here only when the slab is the whole plane.
 template <typename Q2>
-__device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int n1, int cx, int cy, Q2 v,
-                                            bool periodic) {
-    const int c0 = lds_center(rs, cx, cy);
+__device__ __forceinline__ void stage_point(Q2* L, int rs, int n0, int n1, int cx, int cyl, Q2 v,
+                                            bool periodic, bool yghost) {
+    const int c0 = lds_center(rs, cx, cyl);
     L[c0] = v;
     if (!periodic) return;
     if (cx < 6) L[c0 + n0] = v;
     if (cx >= n0 - 6) L[c0 - n0] = v;
-    if (cy < 6) L[c0 + n1 * rs] = v;
-    if (cy >= n1 - 6) L[c0 - n1 * rs] = v;
+    if (!yghost) return;
+    if (cyl < 6) L[c0 + n1 * rs] = v;
+    if (cyl >= n1 - 6) L[c0 - n1 * rs] = v;
 }
 
 // q = (A c) for one column: A = -1/2 Lap_h + V - eps - i omega; x/y neighbours from the
@@ -178,22 +209,50 @@ __device__ __forceinline__ typename Cplx<R>::type stencil(const Args& a, const Q
     return typename Cplx<R>::type{ax + diag * R(c.x) + om * R(c.y), ay + diag * R(c.y) - om * R(c.x)};
 }
 
-// Generic z-march: lead.load(z, i, first) fetches what the queue entry of plane z needs
-// (first: the plane's centre step has not run yet in this sweep), lead.make(buf) turns it
-// into the queue value; cent.load(z, i) fetches what the centre
-// step needs, cent.finish(buf, z, i, c, q) consumes the stencil result.  Loads for step
-// s+1 are issued before step s computes.
+// Generic z-march over the thread's columns of one slab: lead.load(z, i, first) fetches
+// what the queue entry of plane z needs (first: the plane's centre step has not run yet in
+// this sweep), lead.make(buf) turns it into the queue value; cent.load(z, i) fetches what the
+// centre step needs, cent.finish(buf, z, i, c, q) consumes the stencil result.  Loads for step
+// s+1 are issued before step s computes.  With SLAB, the 6 rows above and below the slab are
+// loaded for every centre plane (lead.load_at at a global column) and staged next to the
+// slab's own rows.
 // Q is the caller's queue.  With warm = true it already holds planes -6 .. 5 (mod n2) of the
 // lead vector in Q[0..11] and the warm-up is skipped.  On return Q[0..11] holds planes
 // -6 .. 5 of the lead vector again (the queue has wrapped around the periodic z axis).
-template <typename R, typename Q2, int C, int Z, class Lead, class Cent>
+template <typename R, typename Q2, int C, int Z, bool SLAB, class Lead, class Cent>
 __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds, double eps_n,
                                       Lead& lead, Cent& cent, Q2 (&Q)[12 + Z][C], bool warm) {
     constexpr int NQ = 12 + Z;
     const int n2 = a.n2, P = a.P;
     const R om = R(a.omega);
+    const int tid = threadIdx.x;
+    // slab mode: thread t < 12 n0 loads halo entry t of each centre plane (the launch has
+    // at least 12 n0 threads): rows y0-6 .. y0-1 for t < 6 n0, rows y0+rows .. y0+rows+5 after
+    const int nh = SLAB ? 12 * a.n0 : 0;
+    const bool hv = tid < nh;
+    int hx = 0, lr = 0;
+    unsigned hcol = 0;
+    bool hin = false;
+    if (SLAB && hv) {
+        const int hr = tid / a.n0;
+        hx = tid - hr * a.n0;
+        lr = (hr < 6) ? hr - 6 : a.rows + hr - 6;
+        int gy = cl.y0 + lr;
+        if (a.periodic) {
+            gy += (gy < 0) ? a.n1 : 0;
+            gy -= (gy >= a.n1) ? a.n1 : 0;
+            hin = true;
+        } else {
+            hin = gy >= 0 && gy < a.n1;      // isolated box: rows beyond the walls are zero
+        }
+        hcol = unsigned(gy * a.n0 + hx);
+    }
     typename Lead::Buf LB[Z][C];
     typename Cent::Buf CB[Z][C];
+    typename Lead::Buf HB[Z];
+    auto halo_load = [&](int zc) -> typename Lead::Buf {
+        return hin ? lead.load_at(zc, hcol) : typename Lead::Buf{};
+    };
     // warm-up: push planes -6 .. 5 through the top of the queue, Z at a time
 #pragma unroll 1
     for (int w = 0; w < (warm ? 0 : 12 / Z); ++w) {
@@ -222,12 +281,14 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
                 CB[zz][i] = cent.load(zz, i);
             }
         }
+        if (SLAB) HB[zz] = halo_load(zz);
     }
     const int nsteps = n2 / Z;
 #pragma unroll 1
     for (int st = 0; st < nsteps; ++st) {
         const int zo = st * Z;
         typename Cent::Buf CC[Z][C];
+        Q2 HC[Z];
         if (!RPA_PREFETCH && st > 0) {
 #pragma unroll
             for (int zz = 0; zz < Z; ++zz) {
@@ -241,15 +302,18 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
                                        : typename Lead::Buf{};
                         CB[zz][i] = cent.load(zo + zz, i);
                     }
+                if (SLAB) HB[zz] = halo_load(zo + zz);
             }
         }
 #pragma unroll
-        for (int zz = 0; zz < Z; ++zz)
+        for (int zz = 0; zz < Z; ++zz) {
 #pragma unroll
             for (int i = 0; i < C; ++i) {
                 Q[12 + zz][i] = cl.valid[i] ? lead.make(LB[zz][i]) : Q2{0, 0};
                 CC[zz][i] = CB[zz][i];
             }
+            if (SLAB) HC[zz] = lead.make(HB[zz]);
+        }
         if (RPA_PREFETCH && st + 1 < nsteps) {
 #pragma unroll
             for (int zz = 0; zz < Z; ++zz) {
@@ -266,17 +330,22 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
                         CB[zz][i] = cent.load(zo + Z + zz, i);
                     }
                 }
+                if (SLAB) HB[zz] = halo_load(zo + Z + zz);
             }
         }
-        const int PL = (a.n1 + 12) * a.rs;       // plane with ghost rows and columns
+        const int PL = (a.rows + 12) * a.rs;     // slab plane with ghost rows and columns
         Q2* L = lds + (a.nbuf == 2 ? (st & 1) : 0) * Z * PL;
 #pragma unroll
-        for (int zz = 0; zz < Z; ++zz)
+        for (int zz = 0; zz < Z; ++zz) {
 #pragma unroll
             for (int i = 0; i < C; ++i)
                 if (cl.valid[i])
-                    stage_point(L + zz * PL, a.rs, a.n0, a.n1, cl.cx[i], cl.cy[i], Q[6 + zz][i],
-                                a.periodic != 0);
+                    stage_point(L + zz * PL, a.rs, a.n0, a.n1, cl.cx[i], cl.cyl[i], Q[6 + zz][i],
+                                a.periodic != 0, !SLAB);
+            // halo rows, with their x ghosts when periodic
+            if (SLAB && hv)
+                stage_point(L + zz * PL, a.rs, a.n0, a.n1, hx, lr, HC[zz], a.periodic != 0, false);
+        }
         lds_barrier();
 #pragma unroll
         for (int zz = 0; zz < Z; ++zz) {
@@ -286,7 +355,7 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
                 const unsigned idx = unsigned((zo + zz) * P + cl.col[i]);
                 const R diag = R(a.cw[0] + ld(a.vloc, idx) - eps_n);
                 const auto q = stencil<R, Q2, NQ, C>(a, L + zz * PL, Q, 6 + zz, i, cl.cx[i],
-                                                     cl.cy[i], diag, om);
+                                                     cl.cyl[i], diag, om);
                 cent.finish(CC[zz][i], zo + zz, i, Q[6 + zz][i], q);
                 // one column at a time: keeps the next column's LDS reads (and registers)
                 // behind this column's stores
@@ -308,8 +377,9 @@ template <typename T2, int C>
 struct LeadPnew {
     struct Buf { T2 r, p; };
     const T2* r; const T2* pa; int P; const int* col; bool first; double dbr, dbi;
-    __device__ Buf load(int z, int i, bool) const {
-        const unsigned idx = unsigned(z * P + col[i]);
+    __device__ Buf load(int z, int i, bool) const { return load_at(z, unsigned(col[i])); }
+    __device__ Buf load_at(int z, unsigned gcol) const {
+        const unsigned idx = unsigned(z * P) + gcol;
         Buf b;
         b.r = ld(r, idx);
         b.p = first ? T2{0, 0} : ld(pa, idx);
@@ -347,6 +417,7 @@ struct LeadLoad {
     using Buf = T2;
     const T2* v; int P; const int* col;
     __device__ Buf load(int z, int i, bool) const { return ld(v, unsigned(z * P + col[i])); }
+    __device__ Buf load_at(int z, unsigned gcol) const { return ld(v, unsigned(z * P) + gcol); }
     __device__ T2 make(const Buf& b) const { return b; }
 };
 // x stored as XS (double: real part only, double2: complex FP64, float2: complex64 x_lo)
@@ -393,6 +464,7 @@ struct LeadXlo {
     using Buf = float2;
     const float2* xlo; int P; const int* col;
     __device__ Buf load(int z, int i, bool) const { return ld(xlo, unsigned(z * P + col[i])); }
+    __device__ Buf load_at(int z, unsigned gcol) const { return ld(xlo, unsigned(z * P) + gcol); }
     __device__ float2 make(const Buf& b) const { return b; }
 };
 struct CentRhi {
@@ -443,7 +515,9 @@ __device__ __forceinline__ void fold_xlo(const Args& a, const int (&col)[C], con
 // the FP64 path (double = real part only, double2 = complex); ignored when T = float.
 // OCC = minimum resident waves per SIMD the register allocation must allow (0: derived from
 // BSMAX alone); higher values cap the registers so that two workgroups share a CU.
-template <typename T, typename XS, int C, int Z, int BSMAX, int OCC = 0>
+// SLAB: the plane is marched in a.nslab row slabs one after another (large planes whose
+// whole-plane columns would not fit in registers); otherwise a.nslab = 1 and a.rows = n1.
+template <typename T, typename XS, int C, int Z, int BSMAX, int OCC = 0, bool SLAB = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(64, BSMAX),
                           amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
 void cocg_wg(Args a_in) {
@@ -473,20 +547,31 @@ void cocg_wg(Args a_in) {
     unsigned char* planes = smem_raw + 16 * 8 * sizeof(double);
     const double eps_n = a.eps[sys % a.ns];
 
+    const int nslab = SLAB ? a.nslab : 1;
     Cols<C> cl;
-#pragma unroll
-    for (int i = 0; i < C; ++i) {
-        cl.col[i] = tid + i * BS;
-        cl.valid[i] = cl.col[i] < P;
-        const int cc = cl.valid[i] ? cl.col[i] : 0;
-        cl.cx[i] = cc % n0;
-        cl.cy[i] = cc / n0;
-    }
+    make_cols<C>(a, 0, tid, BS, cl);
+    // In slab mode a sweep reads rows of the swept vector that other threads wrote in the
+    // previous sweep: the end of every sweep is a workgroup-wide memory barrier.
+    auto slab_sync = [&]() {
+        if (SLAB) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+    };
+    // next slab: new columns; the previous slab's last LDS reads finish before the first write
+    auto next_slab = [&](int sl) {
+        if (SLAB) {
+            make_cols<C>(a, sl, tid, BS, cl);
+            if (sl > 0) lds_barrier();
+        }
+    };
 
     if (!a.periodic) {
         // isolated box: every ghost entry of the staged planes reads zero; stage_point never
-        // writes ghosts in this mode, so clearing the plane buffers once suffices
-        const int nent = a.nbuf * Z * (a.n1 + 12) * a.rs;
+        // writes x ghosts in this mode and writes the y ghosts only as zero halo rows, so
+        // clearing the plane buffers once suffices
+        const int nent = a.nbuf * Z * (a.rows + 12) * a.rs;
         double2* pl = reinterpret_cast<double2*>(planes);
         for (int e = tid; e < nent; e += BS) pl[e] = double2{0.0, 0.0};
         lds_barrier();
@@ -506,7 +591,7 @@ void cocg_wg(Args a_in) {
         // ---------------------------------------------------------- sweep 1
         // (isolated box: the queue left by a sweep holds the planes past the top wall, not the
         // planes below the bottom one, so every sweep starts cold)
-        const bool carry = !first && !cold && a.periodic;
+        const bool carry = !SLAB && !first && !cold && a.periodic;
         if (carry) {
             // warm start of sweep 1 from the queue: p_new = r + beta p on planes -6 .. 5,
             // four planes at a time
@@ -534,7 +619,12 @@ void cocg_wg(Args a_in) {
         }
         LeadPnew<T2, C> l1{r, pa, P, cl.col, first, beta_re, beta_im};
         CentSigma<T2, C> c1{pb, P, cl.col, first, {0, 0, 0, 0, 0, 0, 0}};
-        march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q, carry);
+        for (int sl = 0; sl < nslab; ++sl) {
+            next_slab(sl);
+            march<T, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q,
+                                     carry);
+        }
+        slab_sync();
         cold = false;
         wg_reduce<7>(c1.acc, red);
         if (first) {
@@ -563,15 +653,23 @@ void cocg_wg(Args a_in) {
             if constexpr (MIXED) {
                 CentUpdate<T2, float2> c2{r, reinterpret_cast<float2*>(a.xlo) + off, P, cl.col,
                                           xlo_zero, alpha_re, alpha_im, {0, 0, 0}};
-                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q,
-                                   a.periodic != 0);
+                for (int sl = 0; sl < nslab; ++sl) {
+                    next_slab(sl);
+                    march<T, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2,
+                                             Q, !SLAB && a.periodic != 0);
+                }
+                slab_sync();
                 wg_reduce<3>(c2.acc, red);
                 acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
             } else {
                 CentUpdate<T2, XS> c2{r, reinterpret_cast<XS*>(a.x) + off, P, cl.col, first,
                                       alpha_re, alpha_im, {0, 0, 0}};
-                march<T, T2, C, Z>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2, Q,
-                                   a.periodic != 0);
+                for (int sl = 0; sl < nslab; ++sl) {
+                    next_slab(sl);
+                    march<T, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2,
+                                             Q, !SLAB && a.periodic != 0);
+                }
+                slab_sync();
                 wg_reduce<3>(c2.acc, red);
                 acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
             }
@@ -599,8 +697,12 @@ void cocg_wg(Args a_in) {
                     CentRhi cr{reinterpret_cast<double2*>(a.rhi) + off,
                                reinterpret_cast<double2*>(a.x) + off, reinterpret_cast<float2*>(r),
                                P, cl.col, xhi_zero, {0, 0, 0}};
-                    march<double, float2, C, 1>(a, cl, reinterpret_cast<float2*>(planes), eps_n,
-                                                lx, cr, Qx, false);
+                    for (int sl = 0; sl < nslab; ++sl) {
+                        next_slab(sl);
+                        march<double, float2, C, 1, SLAB>(a, cl, reinterpret_cast<float2*>(planes),
+                                                          eps_n, lx, cr, Qx, false);
+                    }
+                    slab_sync();
                     wg_reduce<3>(cr.acc, red);
                     xhi_zero = false;
                     xlo_zero = true;
@@ -637,9 +739,13 @@ void cocg_wg(Args a_in) {
     }
     if constexpr (MIXED) {
         // the solution lives in x_hi: fold the last partial solution if it is pending
-        if (!xlo_zero)
-            fold_xlo<C>(a, cl.col, cl.valid, reinterpret_cast<double2*>(a.x) + off,
-                        reinterpret_cast<const float2*>(a.xlo) + off, xhi_zero);
+        if (!xlo_zero) {
+            for (int sl = 0; sl < nslab; ++sl) {
+                if (SLAB) make_cols<C>(a, sl, tid, BS, cl);
+                fold_xlo<C>(a, cl.col, cl.valid, reinterpret_cast<double2*>(a.x) + off,
+                            reinterpret_cast<const float2*>(a.xlo) + off, xhi_zero);
+            }
+        }
     }
     if (tid == 0) {
         a.iters[sys] = it;
