@@ -179,10 +179,18 @@ struct Chi0Host {
     }
 };
 
-int chunk_vectors(int ns, int nvec, const Opts& o) {
-    int ch = nvec;
-    if (o.max_systems > 0) ch = std::max(1, std::min(nvec, o.max_systems / ns));
-    return ch;
+// COCG state kept in flight when the caller sets no cap: 96 GiB (a third of the HBM of one
+// MI355X), enough for every system of a block at 24^3 and 32^3 and about one frequency's
+// block of 16384 systems at 48^3.
+constexpr double kStateBudget = 96.0 * (1ull << 30);
+
+int chunk_vectors(int64_t nd, int ns, int nvec, const Opts& o) {
+    int cap = o.max_systems;
+    if (cap == 0) {
+        const double per_sys = double(nd) * (o.precision == RPA_MIXED ? 64.0 : 56.0);
+        cap = int(std::min(double(1 << 30), std::floor(kStateBudget / per_sys)));
+    }
+    return std::max(1, std::min(nvec, cap / ns));
 }
 
 int coeff_split(int64_t nd, int ns, int S) {
@@ -194,7 +202,7 @@ int coeff_split(int64_t nd, int ns, int S) {
 
 void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool x_complex,
                 bool with_d, Chi0Buf& b) {
-    b.chunk = chunk_vectors(ns, nvec, o);
+    b.chunk = chunk_vectors(g.nd(), ns, nvec, o);
     const int S = ns * b.chunk;
     const int64_t nd = g.nd();
     b.nsplit = coeff_split(nd, ns, S);

@@ -228,10 +228,22 @@ def cmd_traffic(args):
     out["bytes_per_point_iter"] = (out["fetch_size_bytes_per_point_iter"]
                                    + out["write_size_bytes_per_point_iter"])
     out["apply_stats"] = stats
+    out["workload"] = stats["workload"]
     print(json.dumps(out, indent=1))
     if args.write:
+        # one entry per (precision, workload): replace that entry, keep the others
+        doc = {"kernel": "cocg_wg", "entries": []}
+        if os.path.exists(args.write):
+            with open(args.write) as f:
+                old = json.load(f)
+            if isinstance(old, dict) and isinstance(old.get("entries"), list):
+                doc = old
+        doc["entries"] = [e for e in doc["entries"]
+                          if (e.get("precision"), e.get("workload")) != (out["precision"],
+                                                                        out["workload"])]
+        doc["entries"].append(out)
         with open(args.write, "w") as f:
-            json.dump(out, f, indent=1)
+            json.dump(doc, f, indent=1)
 
 
 def main():
