@@ -179,18 +179,22 @@ struct Chi0Host {
     }
 };
 
-// COCG state kept in flight when the caller sets no cap: 96 GiB (a third of the HBM of one
-// MI355X), enough for every system of a block at 24^3 and 32^3 and about one frequency's
-// block of 16384 systems at 48^3.
-constexpr double kStateBudget = 96.0 * (1ull << 30);
+// COCG state kept in flight when the caller sets no cap: 128 GiB (under half the HBM of one
+// MI355X), enough for every system of a block at 24^3 and 32^3 and for one frequency's block
+// of 16384 systems at 48^3 in either precision.
+constexpr double kStateBudget = 128.0 * (1ull << 30);
 
+// Trial vectors per COCG launch: as many as the cap allows, split into chunks of equal size
+// (a small last chunk would leave most of the GPU idle).
 int chunk_vectors(int64_t nd, int ns, int nvec, const Opts& o) {
     int cap = o.max_systems;
     if (cap == 0) {
         const double per_sys = double(nd) * (o.precision == RPA_MIXED ? 64.0 : 56.0);
         cap = int(std::min(double(1 << 30), std::floor(kStateBudget / per_sys)));
     }
-    return std::max(1, std::min(nvec, cap / ns));
+    const int most = std::max(1, std::min(nvec, cap / ns));
+    const int nch = (nvec + most - 1) / most;
+    return (nvec + nch - 1) / nch;
 }
 
 int coeff_split(int64_t nd, int ns, int S) {
