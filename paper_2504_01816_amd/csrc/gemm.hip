@@ -311,14 +311,101 @@ __global__ void eigbasis_kernel(int n, double h, W7 wt, double* U, double* kappa
 
 }  // namespace
 
+// Projector coefficients when all N_s orbitals fit one 64-row tile (N_s <= 64): the B
+// operand psi_n .* u_j reuses the Psi tile already staged for A.  Per K step the workgroup
+// loads the 64 x 16 Psi tile and the few U columns its 64 output columns touch (columns
+// s = n + ns j of one tile span at most 64/ns + 1 values of j), and each B fragment is formed
+// in the MFMA loop as As[k][n] * Us[k][j - j_first].  Half the global loads of the general
+// loader, no extra barrier.  Same tile, wave and output layout as gemm_f64.
+__global__ __launch_bounds__(256) void gemm_coeff_f64(int ns, int S, int K, int kchunk,
+                                                      const double* __restrict__ psi,
+                                                      const double* __restrict__ U, int64_t nd,
+                                                      double* part, int64_t pstride) {
+    __shared__ double As[BK][BM + 1];
+    __shared__ double Us[BK][BN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int n0 = blockIdx.x * BN, z = blockIdx.z;
+    const int kb = z * kchunk, ke = min(K, kb + kchunk);
+    const int jfirst = n0 / ns;
+    const int nj = min(BN, (min(S, n0 + BN) - 1) / ns - jfirst + 1);   // distinct j in the tile
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+    // this lane's B columns: orbital row in As and U column in Us (fixed over k)
+    int brow[2], bcol[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int gn = min(S - 1, n0 + wn * 32 + j * 16 + (lane & 15));
+        brow[j] = gn % ns;
+        bcol[j] = gn / ns - jfirst;
+    }
+    // tile element e of this thread: k = tid % BK, row = tid / BK + 16 e (k contiguous)
+    double ra[NE], ru[NE];
+    auto load_tiles = [&](int k0) {
+        const int kk = tid % BK, gk = k0 + kk;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int mm = tid / BK + (256 / BK) * e;
+            ra[e] = (mm < ns && gk < ke) ? psi[gk + nd * mm] : 0.0;
+            ru[e] = (mm < nj && gk < ke) ? U[gk + nd * (jfirst + mm)] : 0.0;
+        }
+    };
+    if (kb < ke) load_tiles(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            As[tid % BK][tid / BK + (256 / BK) * e] = ra[e];
+            Us[tid % BK][tid / BK + (256 / BK) * e] = ru[e];
+        }
+        __syncthreads();
+        if (k0 + BK < ke) load_tiles(k0 + BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            const int kr = ks + (lane >> 4);
+            double af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = As[kr][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = As[kr][brow[j]] * Us[kr][bcol[j]];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gm = wm * 32 + i * 16 + (lane >> 4) + 4 * v;
+                const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (gm < ns && gn < S) part[z * pstride + gm + int64_t(ns) * gn] = acc[i][j][v];
+            }
+}
+
 hipError_t launch_proj_coeff(int64_t nd, int ns, int nvec, double dV, const double* psi,
                              const double* U, double* part, int nsplit, double* coeff,
                              hipStream_t s) {
     const int S = ns * nvec;
     const int kchunk = int((nd + nsplit - 1) / nsplit + BK - 1) / BK * BK;
     const int nz = int((nd + kchunk - 1) / kchunk);
-    hipError_t e = run_gemm(ns, S, int(nd), nz, kchunk, PsiT{psi, nd}, PsiU{psi, U, nd, ns},
-                            StorePart{part, int64_t(ns) * S, ns}, s);
+    hipError_t e;
+    if (ns <= BM && S > 0) {
+        hipLaunchKernelGGL(gemm_coeff_f64, dim3(unsigned((S + BN - 1) / BN), 1, unsigned(nz)),
+                           dim3(256), 0, s, ns, S, int(nd), kchunk, psi, U, nd, part,
+                           int64_t(ns) * S);
+        e = hipGetLastError();
+    } else {
+        e = run_gemm(ns, S, int(nd), nz, kchunk, PsiT{psi, nd}, PsiU{psi, U, nd, ns},
+                     StorePart{part, int64_t(ns) * S, ns}, s);
+    }
     if (e != hipSuccess) return e;
     const int64_t n = int64_t(ns) * S;
     hipLaunchKernelGGL(reduce_parts, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, part, nz,

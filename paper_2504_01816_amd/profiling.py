@@ -111,10 +111,12 @@ def cmd_subspace(args):
             json.dump(out, f)
 
 
-# stage of the path -> (substring of the kernel name, flops of one subspace step)
+# stage of the path -> (substrings of the kernel names, separated by |; flops of one subspace
+# step)
 def _stage_flops(nd, n, ns, nr):
     return [
-        ("projector coefficients c = dV Psi^T (psi_n u_j)", "PsiT", 2.0 * nd * ns * ns * nr),
+        ("projector coefficients c = dV Psi^T (psi_n u_j)", "gemm_coeff|PsiT",
+         2.0 * nd * ns * ns * nr),
         ("projected right-hand sides b' = b - Psi c (HBM-bound: writes the COCG start vectors)",
          "CoeffT", 2.0 * nd * ns * ns * nr),
         ("nu^1/2 Kronecker transforms (2 applications x 6 passes; HBM-bound, n/8 flop/B)", "Axis",
@@ -140,12 +142,13 @@ def cmd_stages(args):
     print("| stage | kernels matched | dispatches | time ms | flop | TFLOP/s | of 78.6 |")
     print("|---|---|---|---|---|---|---|")
     for name, key, fl in _stage_flops(info["nd"], info["n"], info["ns"], info["nr"]):
-        ks = [k for k in dur if key in k]
+        ks = [k for k in dur if any(part in k for part in key.split("|"))]
         t = sum(sum(dur[k]) for k in ks)
         nds = sum(len(dur[k]) for k in ks)
         f = fl * it
         print("| %s | `%s` | %d | %.3f | %.3g | %.2f | %.1f%% |" % (
-            name, key, nds, t * 1e3, f, f / t / 1e12 if t else 0, 100 * f / t / 78.6e12 if t else 0))
+            name, key.replace("|", "`, `"), nds, t * 1e3, f, f / t / 1e12 if t else 0,
+            100 * f / t / 78.6e12 if t else 0))
     for key, label in (("cocg_wg", "COCG"), ("drho", "Delta rho"), ("reduce_parts", "split-K reductions"),
                        ("energy_kernel", "energy (Cholesky of I - C)"), ("chol_inv", "Cholesky + inverse")):
         ks = [k for k in dur if key in k]
