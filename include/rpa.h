@@ -124,6 +124,10 @@ typedef struct rpa_stats {
     double cocg_kernel_ms;        /* their summed duration, from HIP events recorded on the
                                      stream of each launch */
     double cocg_point_iters;      /* sum over systems of (COCG iterations x N_d) */
+    int32_t fp64_fallbacks;       /* RPA_MIXED: systems that reached cocg_max_iter in complex64
+                                     and were solved on in FP64 from where they stopped (up
+                                     to cocg_max_iter further iterations) */
+    int32_t reserved;             /* 0 */
 } rpa_stats;
 
 /* Library version (major*10000 + minor*100 + patch). */

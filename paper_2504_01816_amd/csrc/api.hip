@@ -158,6 +158,7 @@ struct Chi0Buf {
     void *r, *pa, *pb, *x;
     void* xlo;      // mixed only
     double* rhi;    // mixed only: complex float64 residual
+    double* b2;     // mixed only: |b|^2 per system, for the FP64 continuation
     int *iters, *status, *refine;
     double* omega_v;  // per trial vector of a chunk: its frequency
     int* order;       // per system of a chunk: dispatch order
@@ -217,12 +218,15 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     b.eps = cv.take<double>(ns);
     b.coeff = cv.take<double>(size_t(ns) * S);
     b.part = cv.take<double>(size_t(b.nsplit) * ns * S);
+    // mixed: r, p_a, p_b, x_lo (complex64) back to back, so that [r | p_a] and [p_b | x_lo]
+    // each hold S x N_d complex128 values for the FP64 continuation of capped systems
     b.r = cv.take<char>(size_t(S) * nd * cplx);
     b.pa = cv.take<char>(size_t(S) * nd * cplx);
     b.pb = cv.take<char>(size_t(S) * nd * cplx);
-    b.x = cv.take<char>(size_t(S) * nd * (b.x_complex ? 16 : 8));
     b.xlo = b.mixed ? cv.take<char>(size_t(S) * nd * 8) : nullptr;
+    b.x = cv.take<char>(size_t(S) * nd * (b.x_complex ? 16 : 8));
     b.rhi = b.mixed ? cv.take<double>(2 * size_t(S) * nd) : nullptr;
+    b.b2 = b.mixed ? cv.take<double>(S) : nullptr;
     b.iters = cv.take<int>(S);
     b.status = cv.take<int>(S);
     b.refine = cv.take<int>(S);
@@ -347,7 +351,7 @@ int coulomb_apply(const Grid& g, const CoulombBuf& b, int power, int nvec, const
 
 struct SolveTally {
     int64_t iters_total = 0, systems = 0, launches = 0, refinements = 0;
-    int iters_max = 0, unconv = 0, breakdown = 0;
+    int iters_max = 0, unconv = 0, breakdown = 0, fallbacks = 0;
     double kernel_ms = 0.0, point_iters = 0.0;
 };
 
@@ -418,6 +422,7 @@ void add_stats(rpa_stats* st, const SolveTally& t) {
     st->cocg_launches += t.launches;
     st->cocg_kernel_ms += t.kernel_ms;
     st->cocg_point_iters += t.point_iters;
+    st->fp64_fallbacks += t.fallbacks;
 }
 
 // Dispatch order of the ns*nv systems of a chunk: the previous apply's iteration counts when
@@ -488,11 +493,76 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
     L.rhi = b.rhi;
     L.refinements = b.refine;
     L.refine_tol = o.refine_tol;
+    L.b2 = b.b2;
     hipEvent_t e0, e1;
     RPA_CHECK(timer_events(&e0, &e1));
     RPA_HIP(hipEventRecord(e0, s));
     RPA_HIP(launch_cocg(L, s));
     RPA_HIP(hipEventRecord(e1, s));
+    return RPA_OK;
+}
+
+// Mixed precision: the systems of a chunk that stopped at the iteration cap (complex64
+// recurrences can lose conjugacy on the most ill-conditioned shifts) are solved on in FP64 from
+// where they stopped: the mixed kernel leaves x_hi and the exact r_hi = b - A x_hi, and the
+// FP64 kernel solves A e = r_hi into x_hi += e to |r| <= tol |b|, with [r | p_a] and
+// [p_b | x_lo] of the mixed state as its two complex128 direction buffers.  Only the capped
+// systems are launched (the dispatch list is their indices).  Needs the host copy of the
+// statuses from tally().
+int continue_capped(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Buf& b,
+                    int nv, bool x_complex, Chi0Host& h, SolveTally& t, hipStream_t s) {
+    if (!b.mixed) return RPA_OK;
+    const int S = cell->n_occ * nv;
+    std::vector<int> capped;
+    for (int i = 0; i < S; ++i)
+        if (h.st[i] == 1) capped.push_back(i);
+    if (capped.empty()) return RPA_OK;
+    RPA_HIP(hipMemcpyAsync(b.order, capped.data(), sizeof(int) * capped.size(),
+                           hipMemcpyHostToDevice, s));
+    CocgLaunch L{};
+    L.g = g;
+    L.nsys = int(capped.size());
+    L.ns = cell->n_occ;
+    L.vloc = cell->v_loc;
+    L.eps = b.eps;
+    L.omega = h.om_chunk[0];
+    L.omega_v = b.omega_v;
+    L.order = b.order;
+    L.tol = o.cocg_tol;
+    L.max_iter = o.cocg_max_iter;
+    L.r = b.rhi;
+    L.pa = b.r;
+    L.pb = b.pb;
+    L.x = b.x;
+    L.x_complex = true;
+    L.iters = b.iters;
+    L.status = b.status;
+    L.fp32 = false;
+    L.b2 = b.b2;
+    L.x_accum = true;
+    (void)x_complex;
+    hipEvent_t e0, e1;
+    RPA_CHECK(timer_events(&e0, &e1));
+    RPA_HIP(hipEventRecord(e0, s));
+    RPA_HIP(launch_cocg(L, s));
+    RPA_HIP(hipEventRecord(e1, s));
+    std::vector<int> it(S), st(S);
+    RPA_HIP(hipMemcpyAsync(it.data(), b.iters, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+    RPA_HIP(hipMemcpyAsync(st.data(), b.status, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+    RPA_HIP(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    RPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+    t.kernel_ms += ms;
+    t.launches += 1;
+    t.fallbacks += int(capped.size());
+    for (int i : capped) {
+        t.point_iters += double(it[i]) * double(g.nd());
+        t.iters_total += it[i];
+        t.iters_max = std::max(t.iters_max, h.it[i] + it[i]);
+        t.unconv -= 1;                 // counted by tally() from the mixed stage
+        t.unconv += (st[i] == 1);
+        t.breakdown += (st[i] == 2);
+    }
     return RPA_OK;
 }
 
@@ -505,9 +575,10 @@ int chi0_apply(const rpa_cell* cell, const Grid& g, int nvec, const double* in, 
     for (int j0 = 0; j0 < nvec; j0 += b.chunk) {
         const int nv = std::min(b.chunk, nvec - j0);
         RPA_CHECK(solve_chunk(cell, g, o, b, in + nd * j0, j0, nv, false, h, s));
+        RPA_CHECK(tally(b, ns * nv, nd, t, h, int64_t(j0) * ns, s));
+        RPA_CHECK(continue_capped(cell, g, o, b, nv, false, h, t, s));
         RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
                             b.x_complex ? 2 : 1, out + nd * j0, s));
-        RPA_CHECK(tally(b, ns * nv, nd, t, h, int64_t(j0) * ns, s));
     }
     return RPA_OK;
 }
@@ -1117,9 +1188,10 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
         for (int j0 = 0; j0 < nr; j0 += b.xb.chunk) {
             const int nv = std::min(b.xb.chunk, nr - j0);
             RPA_CHECK(solve_chunk(cell, g, o, b.xb, b.U + nd * j0, j0, nv, b.xb.x_complex, h, s));
+            RPA_CHECK(tally(b.xb, ns * nv, nd, t, h, int64_t(j0) * ns, s));
+            RPA_CHECK(continue_capped(cell, g, o, b.xb, nv, true, h, t, s));
             RPA_HIP(launch_grad_accum_d(nd, ns, nv, cell->psi, b.xb.eps, omega[m], b.xb.coeff,
                                         b.xb.dbuf, b.coefk + j0, b.xb.x, false, grad_vloc, s));
-            RPA_CHECK(tally(b.xb, ns * nv, nd, t, h, int64_t(j0) * ns, s));
         }
         if (stats) stats->chi0_applies += 1;
     }

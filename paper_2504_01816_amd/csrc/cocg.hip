@@ -193,6 +193,8 @@ hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     a.iters = L.iters;
     a.status = L.status;
     a.refinements = L.refinements;
+    a.b2 = L.b2;
+    a.x_accum = L.x_accum ? 1 : 0;
     Chosen ch = choose(L.g, L.fp32, L.x_complex, true);
     if (!ch.fn) ch = choose(L.g, L.fp32, L.x_complex, false);
     if (!ch.fn) return hipErrorInvalidConfiguration;

@@ -74,6 +74,9 @@ struct Args {
     int periodic;          // 1: periodic cell; 0: isolated box (zero beyond the grid)
     int nslab;             // row slabs a sweep marches one after another (1: whole plane)
     int rows;              // rows per slab (n1 / nslab)
+    double* b2;            // per system |b|^2 (mixed: written; FP64 continuation: read), or null
+    int x_accum;           // FP64 continuation: x accumulates onto its current value and the
+                           // tolerance is relative to b2[sys] instead of the start residual
 };
 
 // Element access through a uniform base pointer and a 32-bit unsigned offset, so loads and
@@ -577,7 +580,7 @@ void cocg_wg(Args a_in) {
         lds_barrier();
     }
 
-    double rho_re = 0, rho_im = 0, bb = 0, beta_re = 0, beta_im = 0, rr_ref = 0;
+    double rho_re = 0, rho_im = 0, bb = 0, beta_re = 0, beta_im = 0, rr_ref = 0, tgt2 = 0;
     int it = 0, st = 0, nref = 0;
     bool xlo_zero = true, xhi_zero = true, done = false;
     bool cold = false;     // the queue was dropped (reliable update): sweep 1 reloads it
@@ -632,6 +635,9 @@ void cocg_wg(Args a_in) {
             rho_im = c1.acc[5];
             bb = c1.acc[6];
             rr_ref = bb;
+            // stopping target |r|^2 <= tol^2 |b|^2; a continuation starts from the residual of
+            // an earlier solve, so its reference is that solve's |b|^2
+            tgt2 = uniform(a.tol2 * ((a.x_accum && a.b2) ? a.b2[sys] : bb));
         }
         const bool zero_rhs = first && !(bb > 0.0);
         bool breakdown = false;
@@ -662,8 +668,8 @@ void cocg_wg(Args a_in) {
                 wg_reduce<3>(c2.acc, red);
                 acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
             } else {
-                CentUpdate<T2, XS> c2{r, reinterpret_cast<XS*>(a.x) + off, P, cl.col, first,
-                                      alpha_re, alpha_im, {0, 0, 0}};
+                CentUpdate<T2, XS> c2{r, reinterpret_cast<XS*>(a.x) + off, P, cl.col,
+                                      first && !a.x_accum, alpha_re, alpha_im, {0, 0, 0}};
                 for (int sl = 0; sl < nslab; ++sl) {
                     next_slab(sl);
                     march<T, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2,
@@ -683,8 +689,10 @@ void cocg_wg(Args a_in) {
         } else {
             bool conv = false;
             if constexpr (MIXED) {
-                // reliable update when the complex64 residual fell by refine_tol or hit tol
-                if (acc2[2] <= a.tol2 * bb || acc2[2] <= a.refine2 * rr_ref) {
+                // reliable update when the complex64 residual fell by refine_tol or hit tol,
+                // and at the iteration cap (so that a stopped solve leaves x_hi and the exact
+                // r_hi = b - A x_hi for an FP64 continuation)
+                if (acc2[2] <= tgt2 || acc2[2] <= a.refine2 * rr_ref || it >= a.max_iter) {
                     // drop the carried queue so that its registers are free for this sweep;
                     // the next sweep 1 reloads its first planes from memory
 #pragma unroll
@@ -709,10 +717,10 @@ void cocg_wg(Args a_in) {
                     ++nref;
                     acc2[0] = cr.acc[0]; acc2[1] = cr.acc[1]; acc2[2] = cr.acc[2];
                     rr_ref = acc2[2];
-                    conv = acc2[2] <= a.tol2 * bb;
+                    conv = acc2[2] <= tgt2;
                 }
             } else {
-                conv = acc2[2] <= a.tol2 * bb;
+                conv = acc2[2] <= tgt2;
             }
             if (conv) {
                 done = true;
@@ -751,6 +759,7 @@ void cocg_wg(Args a_in) {
         a.iters[sys] = it;
         a.status[sys] = st;
         if (a.refinements) a.refinements[sys] = nref;
+        if (MIXED && a.b2) a.b2[sys] = bb;
     }
 }
 

@@ -97,7 +97,9 @@ struct CocgLaunch {
     const double* eps;     // device, ns
     double omega;          // shift of every system unless omega_v is set
     const double* omega_v; // device, nsys / ns: frequency of trial vector j, or null
-    const int* order;      // device, nsys: dispatch order (a permutation of 0..nsys-1), or null
+    const int* order;      // device, nsys: the systems to solve in dispatch order (a
+                           // permutation of 0..nsys-1, or a subset of a larger launch's
+                           // systems), or null
     double tol;
     int max_iter;
     void* r;               // nsys x N_d complex (T2)
@@ -112,6 +114,10 @@ struct CocgLaunch {
     double* rhi;           // mixed: nsys x N_d complex float64 residual (starts at the RHS)
     int* refinements;      // mixed: nsys (may be null)
     double refine_tol;     // mixed: residual drop that triggers a reliable update
+    double* b2;            // per system |b|^2: written by the mixed kernel, read by an
+                           // FP64 continuation (x_accum) as its tolerance reference; or null
+    bool x_accum;          // FP64 continuation: x is added to (not started at 0), and r
+                           // starts at the true residual b - A x
 };
 hipError_t launch_cocg(const CocgLaunch& a, hipStream_t s);
 

@@ -37,7 +37,8 @@ class RpaStats(ctypes.Structure):
                 ("n_breakdown", c_int32), ("refinements", c_int32),
                 ("chi0_applies", c_int32), ("subspace_iters_total", c_int32),
                 ("cocg_launches", c_int64), ("cocg_kernel_ms", c_double),
-                ("cocg_point_iters", c_double)]
+                ("cocg_point_iters", c_double), ("fp64_fallbacks", c_int32),
+                ("reserved", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -229,6 +229,38 @@ def test_mixed_backward_matches_fp64():
     assert rel(gmx.cpu().numpy(), g64.cpu().numpy()) < 1e-8
 
 
+def test_mixed_capped_systems_continue_in_fp64(wl0, dc0):
+    # At omega = 0.02 and tol 1e-10 the oracle needs at most 164 COCG steps, while the
+    # complex64 recurrences of the two orbitals next to the gap need about 240-300; with the
+    # cap at 180 those stop short and the library solves them on in FP64 from where they
+    # stopped (x_hi, r_hi = b - A x_hi) to the same tolerance (a CPU emulation of both stages
+    # puts the continuation at 60-135 steps).
+    c = wl0.cells[0]
+    say("mixed chi0 omega 0.02, cap 180: FP64 continuation of capped systems")
+    U = np.random.default_rng(21).standard_normal((4, c.nd))
+    ref, iters, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, 0.02, c.shape, c.h, 1e-10,
+                                     5000)
+    assert iters.max() < 180
+    out, rc, st = api.rpa_apply_chi0(dc0, 0.02, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-10, cocg_max_iter=180, precision=MIXED))
+    say("fallbacks", st["fp64_fallbacks"], "launches", st["cocg_launches"])
+    assert rc == 0 and st["n_unconverged"] == 0 and st["fp64_fallbacks"] > 0
+    assert st["cocg_launches"] == 2
+    assert rel(out.cpu().numpy().T, ref) < 1e-9
+    # the backward's solves take the same route (complex solutions kept); two solutions
+    # meeting tol 1e-10 differ by up to cond(A) tol ~ 1e-7 at this frequency
+    om, W = np.array([0.02]), np.array([1.0])
+    V = np.linalg.qr(np.random.default_rng(22).standard_normal((c.nd, 4)))[0].T.copy()
+    o = dict(cocg_tol=1e-10, subspace_iters=1, ec_tol=0.0)
+    res = api.rpa_energy(dc0, 4, om, W, [torch.tensor(V, device=DEV)], o, save=True)
+    g64, _, _ = api.rpa_energy_backward(dc0, om, W, res["Vsave"][0], res["Csave"][0], 1.0, o)
+    gmx, rc2, st2 = api.rpa_energy_backward(dc0, om, W, res["Vsave"][0], res["Csave"][0], 1.0,
+                                            dict(o, precision=MIXED, cocg_max_iter=180))
+    say("backward fallbacks", st2["fp64_fallbacks"])
+    assert rc2 == 0 and st2["n_unconverged"] == 0 and st2["fp64_fallbacks"] > 0
+    assert rel(gmx.cpu().numpy(), g64.cpu().numpy()) < 1e-7
+
+
 # ---------------------------------------------------------------------------- batched frequencies
 INDEPENDENT = 1
 
