@@ -102,6 +102,27 @@ def test_workspace_query_is_host_only_and_monotone(so):
     assert out.value < sizes[2]
 
 
+def test_default_state_budget_bounds_the_48_cubed_energy_workspace(so):
+    # 48^3, N_s = 64, N_r = 256, 8 batched frequencies: 131072 systems of 110592 points would
+    # need 811 GB of FP64 COCG state; the default cap keeps one launch within 128 GiB, split
+    # into equal chunks, so the whole energy workspace fits one MI355X (288 GB)
+    c = _cell(n=(48, 48, 48), n_occ=64, h=0.35)
+    nv = (ctypes.c_int32 * 1)(256)
+    for prec, per_pt in ((L.RPA_FP64, 56), (L.RPA_MIXED, 64)):
+        o = L.default_options(freq_mode=L.RPA_INDEPENDENT, precision=prec)
+        out = ctypes.c_size_t(0)
+        assert so.rpa_workspace_size(L.RPA_OP_ENERGY, 1, ctypes.byref(c), nv, 8, ctypes.byref(o),
+                                     ctypes.byref(out)) == 0
+        state = 16384 * 48 ** 3 * per_pt             # one frequency's block in one launch
+        assert state <= out.value < 160 * 2 ** 30, (prec, out.value / 2 ** 30)
+    # an explicit cap below the default takes precedence
+    o = L.default_options(freq_mode=L.RPA_INDEPENDENT, max_systems=4096)
+    small = ctypes.c_size_t(0)
+    assert so.rpa_workspace_size(L.RPA_OP_ENERGY, 1, ctypes.byref(c), nv, 8, ctypes.byref(o),
+                                 ctypes.byref(small)) == 0
+    assert small.value < 4096 * 48 ** 3 * 56 + 40 * 2 ** 30
+
+
 @pytest.mark.parametrize("mut,code", [
     (lambda c: setattr(c, "h", -1.0), L.RPA_EINVAL),
     (lambda c: setattr(c, "n_occ", 0), L.RPA_EINVAL),
