@@ -4,9 +4,10 @@
 //    I - C symmetric positive definite because C <= 0 (Eq. 10)
 //  * cyclic Jacobi eigensolver for the Ritz values and vectors of C (Rayleigh-Ritz)
 //  * Delta rho = 4 sum_n psi_n Re(x_n) (Eq. 8) and the gradient accumulation
-// Each small-matrix kernel runs as one workgroup of 1024 threads on a matrix that stays in
-// L2; N_r is at most a few hundred, so these are latency-bound and a small share of a
-// subspace iteration.
+// Each small-matrix kernel runs as one workgroup of 1024 threads: up to N_r = 90 the
+// matrices are factorised in LDS, beyond that in place in global memory (L2-resident); N_r is
+// at most a few hundred, so these are latency-bound and a small share of a subspace
+// iteration.
 #include "internal.h"
 
 namespace rpa {
@@ -95,6 +96,90 @@ __global__ __launch_bounds__(SB) void energy_kernel(int m, const double* C, doub
     const double s = block_sum(v, red);
     if (threadIdx.x == 0) out[0] = scale * s;
 }
+
+// Small N_r (the whole matrix in LDS): right-looking Cholesky in place on the lower
+// triangle of the m x m column-major LDS matrix A.  sflag = failing column + 1, or 0.
+__device__ void chol_lds(int m, double* A, int* sflag) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int j = 0; j < m; ++j) {
+        if (tid == 0) {
+            const double d = A[j + m * j];
+            if (!(d > 0.0) && *sflag == 0) *sflag = j + 1;
+            A[j + m * j] = (d > 0.0) ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double piv = A[j + m * j];
+        for (int i = j + 1 + tid; i < m; i += bs) A[i + m * j] /= piv;
+        __syncthreads();
+        // trailing update of the lower triangle, columns k and rows i in (j, m), i >= k
+        const int n = m - j - 1;
+        for (int e = tid; e < n * n; e += bs) {
+            const int i = j + 1 + e % n, k = j + 1 + e / n;
+            if (i >= k) A[i + m * k] -= A[i + m * j] * A[k + m * j];
+        }
+        __syncthreads();
+    }
+}
+
+// chol_inv for small m: M -> L (LDS), X = L^{-1} column by column (thread per column,
+// forward substitution from LDS), T = X^T.
+__global__ __launch_bounds__(SB) void chol_inv_lds_kernel(int m, const double* M, double* L,
+                                                          double* T, int* info) {
+    extern __shared__ double sh[];
+    __shared__ int sflag;
+    double* A = sh;
+    double* X = sh + m * m;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int i = tid; i < m * m; i += bs) {
+        const int r = i % m, c = i / m;
+        A[i] = (r >= c) ? M[i] : 0.0;
+    }
+    if (tid == 0) sflag = 0;
+    __syncthreads();
+    chol_lds(m, A, &sflag);
+    for (int c = tid; c < m; c += bs) {
+        X[c + m * c] = 1.0 / A[c + m * c];
+        for (int i = c + 1; i < m; ++i) {
+            double acc = 0.0;
+            for (int k = c; k < i; ++k) acc += A[i + m * k] * X[k + m * c];
+            X[i + m * c] = -acc / A[i + m * i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += bs) {
+        const int r = e % m, c = e / m;
+        T[e] = (c >= r) ? X[c + m * r] : 0.0;
+        L[e] = A[e];
+    }
+    if (tid == 0) *info = sflag;
+}
+
+// energy for small m: Cholesky of I - C in LDS, then ln det + tr.
+__global__ __launch_bounds__(SB) void energy_lds_kernel(int m, const double* C, double scale,
+                                                        double* out, int* info) {
+    extern __shared__ double sh[];
+    __shared__ int sflag;
+    __shared__ double red[SB / 64];
+    double* A = sh;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int i = tid; i < m * m; i += bs) {
+        const int r = i % m, c = i / m;
+        A[i] = (r >= c) ? ((r == c ? 1.0 : 0.0) - C[i]) : 0.0;
+    }
+    if (tid == 0) sflag = 0;
+    __syncthreads();
+    chol_lds(m, A, &sflag);
+    double v = 0.0;
+    for (int i = tid; i < m; i += bs) v += 2.0 * log(A[i + m * i]) + C[i + int64_t(m) * i];
+    const double sum = block_sum(v, red);
+    if (tid == 0) {
+        out[0] = scale * sum;
+        *info = sflag;
+    }
+}
+
+// LDS budget of the small-matrix path (both chol_inv buffers)
+constexpr int kSmallLdsBytes = 128 * 1024;
 
 __global__ void symmetrize_kernel(int m, double* C) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -443,15 +528,31 @@ hipError_t launch_symmetrize(int m, double* C, hipStream_t s) {
 
 hipError_t launch_chol_inv(int m, const double* M, double* L, double* T, int* info,
                            hipStream_t s) {
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(SB), size_t(m) * sizeof(double), s, m, M,
-                       L, T, info);
+    const size_t lds = 2 * size_t(m) * m * sizeof(double);
+    if (lds <= size_t(kSmallLdsBytes)) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(chol_inv_lds_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(chol_inv_lds_kernel, dim3(1), dim3(SB), lds, s, m, M, L, T, info);
+    } else {
+        hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(SB), size_t(m) * sizeof(double), s, m,
+                           M, L, T, info);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_energy_logdet(int m, const double* C, double scale, double* work,
                                 double* out, int* info, hipStream_t s) {
-    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(SB), size_t(m) * sizeof(double), s, m, C,
-                       scale, work, out, info);
+    const size_t lds = size_t(m) * m * sizeof(double);
+    if (2 * lds <= size_t(kSmallLdsBytes)) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(energy_lds_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(energy_lds_kernel, dim3(1), dim3(SB), lds, s, m, C, scale, out, info);
+    } else {
+        hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(SB), size_t(m) * sizeof(double), s, m, C,
+                           scale, work, out, info);
+    }
     return hipGetLastError();
 }
 
