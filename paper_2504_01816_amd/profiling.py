@@ -68,6 +68,10 @@ def cmd_apply(args):
     opts = dict(precision=prec, cocg_tol=wl.cocg_tol)
     tot = {"cocg_point_iters": 0.0, "cocg_launches": 0, "cocg_kernel_ms": 0.0, "cocg_iters_total": 0}
     idx = range(len(wl.omegas)) if args.omega_index < 0 else [args.omega_index]
+    if args.warmup:
+        # one untimed apply first (module load, launch-shape selection); not for counter runs,
+        # whose per-point figures divide by the timed applies' point-iterations
+        api.rpa_apply_chi0(dc, float(wl.omegas[idx[0]]), X, opts)
     for m in idx:
         _, _, st = api.rpa_apply_chi0(dc, float(wl.omegas[m]), X, opts)
         print("omega %.4g: %.2f ms, iterations %d (max %d), reliable updates %d" % (
@@ -262,6 +266,7 @@ def main():
     a.add_argument("--omega-index", type=int, default=-1, help="-1: every frequency")
     a.add_argument("--nvec", type=int, default=0)
     a.add_argument("--out", default="")
+    a.add_argument("--warmup", action="store_true", help="one untimed apply first")
     ss = sub.add_parser("subspace")
     ss.add_argument("--gen-device", action="store_true")
     ss.add_argument("--config", type=int, default=2)
