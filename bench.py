@@ -105,8 +105,9 @@ def cpu_baseline(wl):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only; --gpus %d is not supported (multi-GPU sharding "
-              "is a design note, not part of this build)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only; --gpus %d is not supported (sharding the "
+              "Sternheimer systems across GPUs is described in the design notes, not "
+              "implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 

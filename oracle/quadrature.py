@@ -3,7 +3,7 @@
 Sec. 3: the integral over omega in Eq. 1 / Eq. 10 is approximated by
 Gauss-Legendre quadrature, and the loop over frequencies runs from the highest
 frequency to the lowest (Algorithm 1).  The paper does not state how [-1, 1]
-is mapped onto [0, inf); this build uses the rational map
+is mapped onto [0, inf); the rational map used here is
 
     omega = omega0 (1 + t) / (1 - t),   d omega = 2 omega0 / (1 - t)^2 dt,
 

@@ -81,7 +81,7 @@ def load(path=None):
         return _lib
     p = path or LIB_PATH
     if not os.path.exists(p):
-        raise OSError("librpa_gfx950.so not found at %s: run __graft_entry__.build() first" % p)
+        raise OSError("librpa_gfx950.so not found at %s: build it first (python -m paper_2504_01816_amd.build)" % p)
     lib = ctypes.CDLL(p)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
