@@ -98,8 +98,9 @@ typedef struct rpa_options {
                                 float64 refinements (reliable updates), default 0.1 */
     int32_t max_systems;     /* cap on Sternheimer systems in flight; 0 = as many as keep
                                 the COCG state within 128 GiB (56 B per point and system in
-                                FP64, 64 B mixed); the trial vectors are split into chunks
-                                of equal size under the cap */
+                                FP64, 64 B mixed), shared by the cells of an rpa_energy call
+                                in proportion to their uncapped state; the trial vectors are
+                                split into chunks of equal size under the cap */
     int32_t flags;           /* reserved, 0 */
     int32_t sq_order;        /* 0 (default): E_{c,m} from the Ritz values of C (exact
                                 Rayleigh-Ritz, via ln det(I - C) + tr C); 1..32: Gauss

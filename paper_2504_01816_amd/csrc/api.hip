@@ -50,6 +50,8 @@ struct Opts {
     double refine_tol = 1e-1;
     int max_systems = 0;
     int sq_order = 0;
+    double state_budget = 0.0;   // bytes of COCG state per launch when max_systems = 0 (set
+                                 // below: the library default, or a cell's share of it)
 };
 
 int fail(int code, const std::string& msg) {
@@ -182,16 +184,19 @@ struct Chi0Host {
 
 // COCG state kept in flight when the caller sets no cap: 128 GiB (under half the HBM of one
 // MI355X), enough for every system of a block at 24^3 and 32^3 and for one frequency's block
-// of 16384 systems at 48^3 in either precision.
+// of 16384 systems at 48^3 in either precision.  Cells that run concurrently share it.
 constexpr double kStateBudget = 128.0 * (1ull << 30);
+
+double state_bytes_per_point(const Opts& o) { return o.precision == RPA_MIXED ? 64.0 : 56.0; }
 
 // Trial vectors per COCG launch: as many as the cap allows, split into chunks of equal size
 // (a small last chunk would leave most of the GPU idle).
 int chunk_vectors(int64_t nd, int ns, int nvec, const Opts& o) {
     int cap = o.max_systems;
     if (cap == 0) {
-        const double per_sys = double(nd) * (o.precision == RPA_MIXED ? 64.0 : 56.0);
-        cap = int(std::min(double(1 << 30), std::floor(kStateBudget / per_sys)));
+        const double per_sys = double(nd) * state_bytes_per_point(o);
+        const double budget = o.state_budget > 0.0 ? o.state_budget : kStateBudget;
+        cap = int(std::min(double(1 << 30), std::floor(budget / per_sys)));
     }
     const int most = std::max(1, std::min(nvec, cap / ns));
     const int nch = (nvec + most - 1) / most;
@@ -788,6 +793,27 @@ int energy_batched(const rpa_cell* cell, int nr, int nfreq, const double* omega,
 
 
 // ------------------------------------------------------------------ multi-cell energy
+// Options per cell of a several-cell energy call: without a caller cap the cells, which run
+// concurrently, share the default state budget in proportion to the state their blocks
+// would need uncapped (all frequencies' systems at once in batched mode).
+std::vector<Opts> cell_options(int ncell, const rpa_cell* cells, const int32_t* nr, int nfreq,
+                               const Opts& o) {
+    std::vector<Opts> out(ncell, o);
+    if (ncell < 2 || o.max_systems > 0) return out;
+    std::vector<double> full(ncell);
+    double sum = 0.0;
+    for (int c = 0; c < ncell; ++c) {
+        const Grid g = grid_of(&cells[c]);
+        const double sys = double(cells[c].n_occ) * nr[c] *
+                           (o.freq_mode == RPA_INDEPENDENT ? std::max(1, nfreq) : 1);
+        full[c] = sys * double(g.nd()) * state_bytes_per_point(o);
+        sum += full[c];
+    }
+    if (sum <= kStateBudget) return out;
+    for (int c = 0; c < ncell; ++c) out[c].state_budget = kStateBudget * full[c] / sum;
+    return out;
+}
+
 size_t energy_cell_bytes(const Grid& g, int ns, int nr, int nfreq, const Opts& o) {
     Carver dry;
     if (o.freq_mode == RPA_INDEPENDENT) {
@@ -864,7 +890,7 @@ int energy_cell(CellRun& r, int nfreq, const double* omega, const double* weight
 // them.  Cells are independent, so the results equal those of the one-cell calls; the GPU is
 // shared by the cells' launches instead of running them one after another.
 int energy_cells_concurrent(std::vector<CellRun>& run, int nfreq, const double* omega,
-                            const double* weight, const Opts& o, hipStream_t s) {
+                            const double* weight, const std::vector<Opts>& o, hipStream_t s) {
     int dev = 0;
     RPA_HIP(hipGetDevice(&dev));
     hipEvent_t ready;
@@ -886,7 +912,7 @@ int energy_cells_concurrent(std::vector<CellRun>& run, int nfreq, const double* 
                 run[c].err = "hipSetDevice failed in a cell worker";
                 return;
             }
-            energy_cell(run[c], nfreq, omega, weight, o, st[c]);
+            energy_cell(run[c], nfreq, omega, weight, o[c], st[c]);
             (void)hipEventRecord(done[c], st[c]);
             (void)hipStreamSynchronize(st[c]);
             release_timer();
@@ -961,6 +987,7 @@ int rpa_workspace_size(int32_t op, int32_t ncell, const rpa_cell* cells, const i
     Opts o;
     RPA_CHECK(read_opts(opt, &o));
     size_t need = 0;
+    std::vector<Opts> copt;   // per-cell options of a several-cell energy call
     for (int c = 0; c < ncell; ++c) {
         RPA_CHECK(check_geometry(&cells[c]));
         if (nvec[c] < 1 || nvec[c] > 65535) return fail(RPA_EINVAL, "nvec must be in [1, 65535]");
@@ -974,8 +1001,16 @@ int rpa_workspace_size(int32_t op, int32_t ncell, const rpa_cell* cells, const i
             case RPA_OP_ENERGY: {
                 if (o.freq_mode == RPA_INDEPENDENT && nfreq < 1)
                     return fail(RPA_EINVAL, "nfreq must be >= 1");
+                if (copt.empty()) {
+                    for (int k = 0; k < ncell; ++k) {
+                        RPA_CHECK(check_geometry(&cells[k]));
+                        if (nvec[k] < 1 || nvec[k] > 65535)
+                            return fail(RPA_EINVAL, "nvec must be in [1, 65535]");
+                    }
+                    copt = cell_options(ncell, cells, nvec, std::max(1, int(nfreq)), o);
+                }
                 // cells run concurrently, each in its own slice: the sizes add up
-                need += energy_cell_bytes(g, ns, nvec[c], std::max(1, int(nfreq)), o);
+                need += energy_cell_bytes(g, ns, nvec[c], std::max(1, int(nfreq)), copt[c]);
                 continue;
             }
             case RPA_OP_BACKWARD: {
@@ -1084,16 +1119,19 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
     }
     Opts o;
     RPA_CHECK(read_opts(opt, &o));
-    // each cell works in its own slice of the workspace (256-byte aligned offsets)
-    std::vector<size_t> offs(ncell + 1, 0);
     for (int c = 0; c < ncell; ++c) {
         RPA_CHECK(check_cell(&cells[c]));
         const Grid g = grid_of(&cells[c]);
         if (nr[c] < 1 || nr[c] > 4096 || nr[c] > g.nd())
             return fail(RPA_EINVAL, "nr must be in [1, min(4096, N_d)]");
         if (!V0[c]) return fail(RPA_EINVAL, "V0 pointer is NULL");
-        offs[c + 1] = offs[c] + energy_cell_bytes(g, cells[c].n_occ, nr[c], nfreq, o);
     }
+    const std::vector<Opts> copt = cell_options(ncell, cells, nr, nfreq, o);
+    // each cell works in its own slice of the workspace (256-byte aligned offsets)
+    std::vector<size_t> offs(ncell + 1, 0);
+    for (int c = 0; c < ncell; ++c)
+        offs[c + 1] = offs[c] + energy_cell_bytes(grid_of(&cells[c]), cells[c].n_occ, nr[c], nfreq,
+                                                  copt[c]);
     RPA_CHECK(check_ws(ws, ws_bytes, offs[ncell]));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<CellRun> run(ncell);
@@ -1110,9 +1148,9 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
     }
     int rc;
     if (ncell == 1) {
-        rc = energy_cell(run[0], nfreq, omega, weight, o, s);
+        rc = energy_cell(run[0], nfreq, omega, weight, copt[0], s);
     } else {
-        rc = energy_cells_concurrent(run, nfreq, omega, weight, o, s);
+        rc = energy_cells_concurrent(run, nfreq, omega, weight, copt, s);
     }
     SolveTally t;
     for (int c = 0; c < ncell; ++c) {
@@ -1126,6 +1164,7 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
         t.breakdown += r.t.breakdown;
         t.kernel_ms += r.t.kernel_ms;
         t.point_iters += r.t.point_iters;
+        t.fallbacks += r.t.fallbacks;
         if (stats) {
             stats->chi0_applies += r.applies;
             stats->subspace_iters_total += r.applies;

@@ -123,6 +123,27 @@ def test_default_state_budget_bounds_the_48_cubed_energy_workspace(so):
     assert small.value < 4096 * 48 ** 3 * 56 + 40 * 2 ** 30
 
 
+def test_concurrent_cells_share_the_default_state_budget(so):
+    # the six-cell batching workload (20^3 .. 40^3, N_r = 4 N_s, 8 batched frequencies) would
+    # need about 310 GB of FP64 COCG state uncapped; run concurrently, the cells share the
+    # 128 GiB default budget, so the whole workspace fits one MI355X
+    grids, occ = [20, 24, 28, 32, 36, 40], [8, 12, 20, 28, 36, 48]
+    cells = (L.RpaCell * 6)()
+    keep = []
+    for i, (g, o) in enumerate(zip(grids, occ)):
+        c = _cell(n=(g, g, g), n_occ=o, h=0.4)
+        keep.append(c)
+        cells[i] = c
+    nv = (ctypes.c_int32 * 6)(*[4 * o for o in occ])
+    uncapped = sum(8 * o * 4 * o * g ** 3 * 56 for g, o in zip(grids, occ))
+    assert uncapped > 300e9
+    out = ctypes.c_size_t(0)
+    o = L.default_options(freq_mode=L.RPA_INDEPENDENT)
+    assert so.rpa_workspace_size(L.RPA_OP_ENERGY, 6, cells, nv, 8, ctypes.byref(o),
+                                 ctypes.byref(out)) == 0
+    assert 100 * 2 ** 30 < out.value < 150 * 2 ** 30, out.value / 2 ** 30
+
+
 @pytest.mark.parametrize("mut,code", [
     (lambda c: setattr(c, "h", -1.0), L.RPA_EINVAL),
     (lambda c: setattr(c, "n_occ", 0), L.RPA_EINVAL),
