@@ -62,6 +62,12 @@ extern "C" {
 #define RPA_INDEPENDENT   1   /* every frequency starts from V0; all frequencies still
                                  iterating share one batched chi0 launch per iteration */
 
+/* rpa_options.flags */
+#define RPA_FLAG_PRECOND  1   /* Sternheimer solves by COCG preconditioned with the Kronecker
+                                 shifted Laplacian K = -1/2 Lap_h + sigma_n - i omega,
+                                 sigma_n = max(mean V_loc - eps_n, 1/2) (Sec. 3's
+                                 Laplacian-based preconditioning); RPA_FP64 only */
+
 #define RPA_BC_PERIODIC   0   /* periodic cell */
 #define RPA_BC_DIRICHLET  1   /* isolated box (zero outside the grid) */
 
@@ -101,7 +107,7 @@ typedef struct rpa_options {
                                 FP64, 64 B mixed), shared by the cells of an rpa_energy call
                                 in proportion to their uncapped state; the trial vectors are
                                 split into chunks of equal size under the cap */
-    int32_t flags;           /* reserved, 0 */
+    int32_t flags;           /* 0 or RPA_FLAG_PRECOND */
     int32_t sq_order;        /* 0 (default): E_{c,m} from the Ritz values of C (exact
                                 Rayleigh-Ritz, via ln det(I - C) + tr C); 1..32: Gauss
                                 spectral quadrature of that order on C (Sec. 3, Algorithm 1:

@@ -52,6 +52,7 @@ struct Opts {
     int sq_order = 0;
     double state_budget = 0.0;   // bytes of COCG state per launch when max_systems = 0 (set
                                  // below: the library default, or a cell's share of it)
+    bool precond = false;        // RPA_FLAG_PRECOND
 };
 
 int fail(int code, const std::string& msg) {
@@ -71,6 +72,8 @@ int read_opts(const rpa_options* o, Opts* out) {
         d.refine_tol = o->refine_tol;
         d.max_systems = o->max_systems;
         d.sq_order = o->sq_order;
+        if (o->flags & ~RPA_FLAG_PRECOND) return fail(RPA_EINVAL, "options.flags: unknown bits");
+        d.precond = (o->flags & RPA_FLAG_PRECOND) != 0;
     }
     if (d.precision != RPA_FP64 && d.precision != RPA_MIXED)
         return fail(RPA_EINVAL, "options.precision must be RPA_FP64 or RPA_MIXED");
@@ -86,6 +89,8 @@ int read_opts(const rpa_options* o, Opts* out) {
     if (d.max_systems < 0) return fail(RPA_EINVAL, "options.max_systems must be >= 0");
     if (d.sq_order < 0 || d.sq_order > 32)
         return fail(RPA_EINVAL, "options.sq_order must be in [0, 32]");
+    if (d.precond && d.precision != RPA_FP64)
+        return fail(RPA_ENOTIMPL, "RPA_FLAG_PRECOND is implemented for RPA_FP64 only");
     *out = d;
     return RPA_OK;
 }
@@ -165,6 +170,14 @@ struct Chi0Buf {
     double* omega_v;  // per trial vector of a chunk: its frequency
     int* order;       // per system of a chunk: dispatch order
     double2* dbuf;  // backward only
+    // preconditioned solver (RPA_FLAG_PRECOND): split complex vectors, per-system scalars,
+    // the 1D eigenbases of the preconditioner and the mean of V_loc
+    bool precond;
+    double *pr, *pp, *pz, *pq, *ptmp;
+    double2 *prho, *kshift;
+    double* pb2;
+    int* pactive;
+    double *Ux, *Uy, *Uz, *kx, *ky, *kz, *bwork, *vmean;
 };
 
 // Host side of a chi0 apply: the frequency of every trial vector, and per system (n + ns j
@@ -176,6 +189,8 @@ struct Chi0Host {
     std::vector<int> hint;
     std::vector<double> om_chunk;
     std::vector<int> order, it, st, rf;
+    double vmean = 0.0;               // mean V_loc (preconditioner shifts)
+    std::vector<double2> kshift;      // per system of a chunk: (sigma_n, omega_j)
     void reset(int ns, int nvec, double w) {
         omega.assign(nvec, w);
         hint.assign(size_t(ns) * nvec, -1);
@@ -187,7 +202,11 @@ struct Chi0Host {
 // of 16384 systems at 48^3 in either precision.  Cells that run concurrently share it.
 constexpr double kStateBudget = 128.0 * (1ull << 30);
 
-double state_bytes_per_point(const Opts& o) { return o.precision == RPA_MIXED ? 64.0 : 56.0; }
+// COCG state per point and system: FP64 r, p_a, p_b complex128 + x; mixed 64 B; the
+// preconditioned solver keeps r, p, z, q, a transform buffer, x and b: 112 B.
+double state_bytes_per_point(const Opts& o) {
+    return o.precond ? 112.0 : (o.precision == RPA_MIXED ? 64.0 : 56.0);
+}
 
 // Trial vectors per COCG launch: as many as the cap allows, split into chunks of equal size
 // (a small last chunk would leave most of the GPU idle).
@@ -217,8 +236,10 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     const int64_t nd = g.nd();
     b.nsplit = coeff_split(nd, ns, S);
     b.mixed = (o.precision == RPA_MIXED);
-    // the mixed path keeps its solution as complex float64 (x_hi) for the true residual
-    b.x_complex = x_complex || b.mixed;
+    b.precond = o.precond;
+    // the mixed path keeps its solution as complex float64 (x_hi) for the true residual; the
+    // preconditioned solver keeps it complex as well
+    b.x_complex = x_complex || b.mixed || b.precond;
     const size_t cplx = b.mixed ? 8 : 16;
     b.eps = cv.take<double>(ns);
     b.coeff = cv.take<double>(size_t(ns) * S);
@@ -238,6 +259,33 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     b.omega_v = cv.take<double>(b.chunk);
     b.order = cv.take<int>(S);
     b.dbuf = with_d ? cv.take<double2>(size_t(ns) * S) : nullptr;
+    if (b.precond) {
+        const size_t blk = 2 * size_t(S) * nd;
+        b.pr = cv.take<double>(blk);
+        b.pp = cv.take<double>(blk);
+        b.pz = cv.take<double>(blk);
+        b.pq = cv.take<double>(blk);
+        b.ptmp = cv.take<double>(blk);
+        b.prho = cv.take<double2>(S);
+        b.kshift = cv.take<double2>(S);
+        b.pb2 = cv.take<double>(S);
+        b.pactive = cv.take<int>(S);
+        b.Ux = cv.take<double>(size_t(g.n0) * g.n0);
+        b.Uy = cv.take<double>(size_t(g.n1) * g.n1);
+        b.Uz = cv.take<double>(size_t(g.n2) * g.n2);
+        b.kx = cv.take<double>(g.n0);
+        b.ky = cv.take<double>(g.n1);
+        b.kz = cv.take<double>(g.n2);
+        const size_t nm = size_t(std::max(g.n0, std::max(g.n1, g.n2)));
+        b.bwork = g.periodic() ? nullptr : cv.take<double>(3 * nm * nm);
+        b.vmean = cv.take<double>(1);
+    } else {
+        b.pr = b.pp = b.pz = b.pq = b.ptmp = nullptr;
+        b.prho = b.kshift = nullptr;
+        b.pb2 = nullptr;
+        b.pactive = nullptr;
+        b.Ux = b.Uy = b.Uz = b.kx = b.ky = b.kz = b.bwork = b.vmean = nullptr;
+    }
 }
 
 int gram_split(int64_t nd, int m) {
@@ -470,6 +518,49 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
         RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff,
                                         reinterpret_cast<double*>(b.r), nullptr, s));
     h.om_chunk.assign(h.omega.begin() + j0, h.omega.begin() + j0 + nv);
+    if (b.precond) {
+        RPA_HIP(hipMemcpyAsync(b.omega_v, h.om_chunk.data(), sizeof(double) * nv,
+                               hipMemcpyHostToDevice, s));
+        h.kshift.resize(size_t(ns) * nv);
+        for (int i = 0; i < ns * nv; ++i)
+            h.kshift[i] = double2{std::max(h.vmean - cell->eps[i % ns], 0.5), h.om_chunk[i / ns]};
+        RPA_HIP(hipMemcpyAsync(b.kshift, h.kshift.data(), sizeof(double2) * ns * nv,
+                               hipMemcpyHostToDevice, s));
+        PcocgLaunch P{};
+        P.g = g;
+        P.nsys = ns * nv;
+        P.ns = ns;
+        P.vloc = cell->v_loc;
+        P.eps = b.eps;
+        P.omega_v = b.omega_v;
+        P.kshift = b.kshift;
+        P.tol = o.cocg_tol;
+        P.max_iter = o.cocg_max_iter;
+        P.rhs = reinterpret_cast<const double2*>(b.r);
+        P.x = reinterpret_cast<double2*>(b.x);
+        P.r = b.pr;
+        P.p = b.pp;
+        P.z = b.pz;
+        P.q = b.pq;
+        P.tmp = b.ptmp;
+        P.rho = b.prho;
+        P.b2 = b.pb2;
+        P.active = b.pactive;
+        P.iters = b.iters;
+        P.status = b.status;
+        P.Ux = b.Ux;
+        P.Uy = b.Uy;
+        P.Uz = b.Uz;
+        P.kx = b.kx;
+        P.ky = b.ky;
+        P.kz = b.kz;
+        hipEvent_t e0, e1;
+        RPA_CHECK(timer_events(&e0, &e1));
+        RPA_HIP(hipEventRecord(e0, s));
+        RPA_HIP(launch_pcocg(P, s));
+        RPA_HIP(hipEventRecord(e1, s));
+        return RPA_OK;
+    }
     dispatch_order(cell, nv, j0, h);
     RPA_HIP(hipMemcpyAsync(b.omega_v, h.om_chunk.data(), sizeof(double) * nv,
                            hipMemcpyHostToDevice, s));
@@ -504,6 +595,26 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
     RPA_HIP(hipEventRecord(e0, s));
     RPA_HIP(launch_cocg(L, s));
     RPA_HIP(hipEventRecord(e1, s));
+    return RPA_OK;
+}
+
+// Preconditioned solver: the 1D eigenbases of the shifted Laplacian (as for nu^{1/2}) and
+// the mean of V_loc for the shifts sigma_n = max(mean V_loc - eps_n, 1/2).
+int precond_setup(const rpa_cell* cell, const Grid& g, const Chi0Buf& b, Chi0Host& h,
+                  hipStream_t s) {
+    if (!b.precond) return RPA_OK;
+    if (g.periodic()) {
+        RPA_HIP(launch_eigbasis_1d(g.n0, g.h, b.Ux, b.kx, s));
+        RPA_HIP(launch_eigbasis_1d(g.n1, g.h, b.Uy, b.ky, s));
+        RPA_HIP(launch_eigbasis_1d(g.n2, g.h, b.Uz, b.kz, s));
+    } else {
+        RPA_HIP(launch_eigbasis_1d_box(g.n0, g.h, b.Ux, b.kx, b.bwork, s));
+        RPA_HIP(launch_eigbasis_1d_box(g.n1, g.h, b.Uy, b.ky, b.bwork, s));
+        RPA_HIP(launch_eigbasis_1d_box(g.n2, g.h, b.Uz, b.kz, b.bwork, s));
+    }
+    RPA_HIP(launch_vloc_mean(g.nd(), cell->v_loc, b.vmean, s));
+    RPA_HIP(hipMemcpyAsync(&h.vmean, b.vmean, sizeof(double), hipMemcpyDeviceToHost, s));
+    RPA_HIP(hipStreamSynchronize(s));
     return RPA_OK;
 }
 
@@ -577,6 +688,7 @@ int chi0_apply(const rpa_cell* cell, const Grid& g, int nvec, const double* in, 
     const int ns = cell->n_occ;
     const int64_t nd = g.nd();
     RPA_HIP(hipMemcpyAsync(b.eps, cell->eps, sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    RPA_CHECK(precond_setup(cell, g, b, h, s));
     for (int j0 = 0; j0 < nvec; j0 += b.chunk) {
         const int nv = std::min(b.chunk, nvec - j0);
         RPA_CHECK(solve_chunk(cell, g, o, b, in + nd * j0, j0, nv, false, h, s));
@@ -1213,6 +1325,7 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
     RPA_HIP(launch_fill(nd, 0.0, grad_vloc, s));
     std::vector<double> mu(nr), ck(nr);
     Chi0Host h;
+    RPA_CHECK(precond_setup(cell, g, b.xb, h, s));
     for (int m = 0; m < nfreq; ++m) {
         h.reset(ns, nr, omega[m]);
         const double* Vm = Vsave + size_t(m) * nd * nr;

@@ -275,6 +275,27 @@ __global__ void kron_scale(double* X, int n0, int n1, int n2, int64_t total, con
     X[i] *= s;
 }
 
+// Preconditioner scale on the mode grid: columns 2t and 2t+1 are the real and imaginary
+// parts of system t; each mode is divided by 1/2 (kx + ky + kz) + sigma_t - i omega_t, with
+// kshift[t] = (sigma_t, omega_t).
+__global__ void precond_scale(double* X, int n0, int n1, int n2, int64_t npair,
+                              const double* kx, const double* ky, const double* kz,
+                              const double2* kshift) {
+    const int64_t nd = int64_t(n0) * n1 * n2;
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= nd * npair) return;
+    const int64_t p = i % nd, t = i / nd;
+    const int x = int(p % n0), y = int((p / n0) % n1), z = int(p / (int64_t(n0) * n1));
+    const double2 ks = kshift[t];
+    const double d = 0.5 * (kx[x] + ky[y] + kz[z]) + ks.x, w = ks.y;
+    const double den = 1.0 / (d * d + w * w);
+    double* re = X + p + nd * (2 * t);
+    double* im = re + nd;
+    const double a = *re, b = *im;
+    *re = (a * d - b * w) * den;
+    *im = (b * d + a * w) * den;
+}
+
 struct W7 {
     double w[7];
 };
@@ -475,7 +496,7 @@ hipError_t launch_eigbasis_1d_box(int n, double h, double* U, double* kappa, dou
 static hipError_t kron_chunk(const Grid& g, int power, int nvec, const double* in, double* out,
                              double* tmp, const double* Ux, const double* Uy, const double* Uz,
                              const double* kx, const double* ky, const double* kz,
-                             hipStream_t s) {
+                             hipStream_t s, const double2* kshift = nullptr) {
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2, P = n0 * n1;
     const int rows_x = n1 * n2 * nvec;
     hipError_t e;
@@ -491,8 +512,12 @@ static hipError_t kron_chunk(const Grid& g, int power, int nvec, const double* i
                  s);
     if (e != hipSuccess) return e;
     const int64_t total = g.nd() * nvec;
-    hipLaunchKernelGGL(kron_scale, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, tmp, n0,
-                       n1, n2, total, kx, ky, kz, power, g.periodic() ? 1 : 0);
+    if (kshift)
+        hipLaunchKernelGGL(precond_scale, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s,
+                           tmp, n0, n1, n2, int64_t(nvec / 2), kx, ky, kz, kshift);
+    else
+        hipLaunchKernelGGL(kron_scale, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, tmp,
+                           n0, n1, n2, total, kx, ky, kz, power, g.periodic() ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // inverse z, y, x
@@ -520,6 +545,26 @@ hipError_t launch_kron_apply(const Grid& g, int power, int nvec, const double* i
         const int nv = std::min(chunk, nvec - j0);
         hipError_t e = kron_chunk(g, power, nv, in + nd * j0, out + nd * j0, tmp + nd * j0, Ux, Uy,
                                   Uz, kx, ky, kz, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_kron_precond(const Grid& g, int nsys, const double* in, double* out,
+                               double* tmp, const double* Ux, const double* Uy, const double* Uz,
+                               const double* kx, const double* ky, const double* kz,
+                               const double2* kshift, hipStream_t s) {
+    // as launch_kron_apply, on 2 nsys columns kept in (real, imaginary) pairs per chunk
+    const int64_t lim_y = 65535 / g.n2;
+    const int64_t lim_x = (int64_t(65535) * BM) / (int64_t(g.n1) * g.n2);
+    const int64_t ncol = 2 * int64_t(nsys);
+    int chunk = int(std::max<int64_t>(2, std::min<int64_t>({ncol, lim_y, lim_x})));
+    chunk -= chunk % 2;
+    const int64_t nd = g.nd();
+    for (int64_t j0 = 0; j0 < ncol; j0 += chunk) {
+        const int nv = int(std::min<int64_t>(chunk, ncol - j0));
+        hipError_t e = kron_chunk(g, 0, nv, in + nd * j0, out + nd * j0, tmp + nd * j0, Ux, Uy,
+                                  Uz, kx, ky, kz, s, kshift + j0 / 2);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -75,6 +75,39 @@ hipError_t launch_kron_apply(const Grid& g, int power, int nvec, const double* i
                              double* tmp, const double* Ux, const double* Uy, const double* Uz,
                              const double* kx, const double* ky, const double* kz,
                              hipStream_t s);
+// Shifted-Laplacian preconditioner on nsys complex vectors stored as N_d x 2 nsys real
+// columns (real and imaginary part of system t in columns 2t, 2t+1): out = K_t^{-1} in with
+// K_t = -1/2 Lap_h + kshift[t].x - i kshift[t].y, through the same 1D eigenbases.
+hipError_t launch_kron_precond(const Grid& g, int nsys, const double* in, double* out,
+                               double* tmp, const double* Ux, const double* Uy, const double* Uz,
+                               const double* kx, const double* ky, const double* kz,
+                               const double2* kshift, hipStream_t s);
+
+// Preconditioned COCG (Kronecker shifted-Laplacian preconditioner) on nsys systems, FP64,
+// host-driven iterations of batched kernels (one workgroup per system for the stencil,
+// reductions and updates; the preconditioner as Kronecker passes over all systems).  The
+// complex vectors r, p, z, q live as N_d x 2 nsys real column blocks.  See pcocg.hip.
+struct PcocgLaunch {
+    Grid g;
+    int nsys, ns;
+    const double* vloc;
+    const double* eps;      // device, ns
+    const double* omega_v;  // device, nsys / ns: frequency of trial vector j
+    const double2* kshift;  // device, nsys: (sigma, omega) of each system's preconditioner
+    double tol;
+    int max_iter;
+    const double2* rhs;     // nsys x N_d complex (interleaved): right-hand sides
+    double2* x;             // nsys x N_d complex (interleaved): solutions
+    double *r, *p, *z, *q, *tmp;   // N_d x 2 nsys each
+    double2* rho;           // nsys
+    double* b2;             // nsys
+    int *active, *iters, *status;  // nsys
+    const double *Ux, *Uy, *Uz, *kx, *ky, *kz;
+};
+// Runs the whole solve (synchronises the stream every few iterations to test for the end).
+hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s);
+// mean of V_loc into *out (device)
+hipError_t launch_vloc_mean(int64_t nd, const double* vloc, double* out, hipStream_t s);
 
 // Occupied projector: coeff[l + ns*s] = dV sum_r psi[r,l] psi[r,n(s)] u[r,j(s)],
 // s = n + ns*j, for j in [0, nvec).  part: split-K partial buffer (nsplit*ns*ns*nvec).

@@ -1,0 +1,312 @@
+// Preconditioned COCG for the Sternheimer systems (H - eps_n - i omega) x = b with the
+// Kronecker shifted-Laplacian preconditioner K_s^{-1}, K_s = -1/2 Lap_h + sigma_n - i omega
+// (the Laplacian-based preconditioning through the Kronecker product formalism that Sec. 3
+// offers as an alternative to the projector-based initial guess).  K_s is complex
+// symmetric, so the iteration keeps COCG's unconjugated bilinear form:
+//
+//     r = b, z = M r, p = z, rho = r^T z
+//     repeat:  q = A p; alpha = rho / p^T q; x += alpha p; r -= alpha q   (pc_step)
+//              stop when ||r|| <= tol ||b||
+//              z = M r                                                  (Kronecker passes)
+//              rho' = r^T z; p = z + (rho'/rho) p                       (pc_rz)
+//
+// Design: the preconditioner needs whole-vector transforms along every axis, which do not
+// fit the register-resident z-march of the plain COCG kernel, so each iteration is a few
+// batched launches driven by the host: pc_step and pc_rz run one workgroup per system (the
+// stencil gathers its 36 neighbours through the caches, reductions are workgroup-local and
+// in a fixed order), and z = M r is 3 + 3 Kronecker GEMM passes with a diagonal scale over
+// all systems at once.  Every thread touches the same points in both loops of a kernel, so
+// a value a thread writes is read back only by itself.  Converged systems drop out of the
+// per-system kernels; the host tests for the end every few iterations.
+// Layout: r, p, z, q as N_d x 2 nsys real columns (real, imaginary part of system s in
+// columns 2s, 2s+1); x and the right-hand sides complex interleaved, nsys x N_d.
+#include <vector>
+
+#include "internal.h"
+
+namespace rpa {
+namespace {
+
+constexpr int PB = 256;
+constexpr int kCheckEvery = 8;   // iterations between tests for the end
+
+struct PcArgs {
+    int n0, n1, n2, periodic;
+    int64_t nd;
+    double cw[7];   // cw[k] = -1/2 w_k / h^2 (k >= 1); cw[0] = -1/2 * 3 w_0 / h^2
+    const double* vloc;
+    const double* eps;
+    const double* omega_v;
+    int ns;
+    double tol2, bd_tol;
+    int max_iter;
+    double *r, *p, *z, *q;
+    double2* x;
+    const double2* rhs;
+    double2* rho;
+    double* b2;
+    int *active, *iters, *status;
+};
+
+// Sum of NV values over the workgroup, in a fixed order (wave butterfly, then waves in order);
+// every thread receives the sums.
+template <int NV>
+__device__ void pc_reduce(double (&v)[NV], double* red) {
+    for (int o = 32; o > 0; o >>= 1)
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+    __syncthreads();
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * NV + k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// r = b (split), x = 0, |b|^2; systems with b = 0 are done (x = 0).
+__global__ __launch_bounds__(PB) void pc_start(PcArgs a) {
+    __shared__ double red[(PB / 64) * 1];
+    const int s = blockIdx.x;
+    const int64_t nd = a.nd;
+    const double2* b = a.rhs + int64_t(s) * nd;
+    double* rr = a.r + nd * (2 * int64_t(s));
+    double* ri = rr + nd;
+    double2* x = a.x + int64_t(s) * nd;
+    double acc[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < nd; i += PB) {
+        const double2 v = b[i];
+        rr[i] = v.x;
+        ri[i] = v.y;
+        x[i] = double2{0.0, 0.0};
+        acc[0] += v.x * v.x + v.y * v.y;
+    }
+    pc_reduce<1>(acc, red);
+    if (threadIdx.x == 0) {
+        a.b2[s] = acc[0];
+        a.active[s] = acc[0] > 0.0 ? 1 : 0;
+        a.iters[s] = 0;
+        a.status[s] = 0;
+    }
+}
+
+// One neighbour value of the split vector v at (x + dx, y + dy, z + dz); 0 beyond the walls of
+// an isolated box.
+__device__ __forceinline__ double nb(const double* v, const PcArgs& a, int x, int y, int z) {
+    if (a.periodic) {
+        x += (x < 0) ? a.n0 : 0;
+        x -= (x >= a.n0) ? a.n0 : 0;
+        y += (y < 0) ? a.n1 : 0;
+        y -= (y >= a.n1) ? a.n1 : 0;
+        z += (z < 0) ? a.n2 : 0;
+        z -= (z >= a.n2) ? a.n2 : 0;
+    } else if (x < 0 || x >= a.n0 || y < 0 || y >= a.n1 || z < 0 || z >= a.n2) {
+        return 0.0;
+    }
+    return v[x + int64_t(a.n0) * (y + int64_t(a.n1) * z)];
+}
+
+// q = A p, sigma = p^T q; alpha = rho / sigma; x += alpha p; r -= alpha q; convergence test.
+__global__ __launch_bounds__(PB) void pc_step(PcArgs a, int it) {
+    __shared__ double red[(PB / 64) * 4];
+    const int s = blockIdx.x;
+    if (!a.active[s]) return;
+    const int64_t nd = a.nd;
+    const double eps = a.eps[s % a.ns], om = a.omega_v[s / a.ns];
+    const double* pr = a.p + nd * (2 * int64_t(s));
+    const double* pi = pr + nd;
+    double* qr = a.q + nd * (2 * int64_t(s));
+    double* qi = qr + nd;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sigma re/im, |p|^2, |q|^2
+    for (int64_t i = threadIdx.x; i < nd; i += PB) {
+        const int x = int(i % a.n0), y = int((i / a.n0) % a.n1), z = int(i / (int64_t(a.n0) * a.n1));
+        double sr = 0.0, si = 0.0;
+        for (int k = 1; k <= 6; ++k) {
+            const double tr = nb(pr, a, x + k, y, z) + nb(pr, a, x - k, y, z) +
+                              nb(pr, a, x, y + k, z) + nb(pr, a, x, y - k, z) +
+                              nb(pr, a, x, y, z + k) + nb(pr, a, x, y, z - k);
+            const double ti = nb(pi, a, x + k, y, z) + nb(pi, a, x - k, y, z) +
+                              nb(pi, a, x, y + k, z) + nb(pi, a, x, y - k, z) +
+                              nb(pi, a, x, y, z + k) + nb(pi, a, x, y, z - k);
+            sr += a.cw[k] * tr;
+            si += a.cw[k] * ti;
+        }
+        const double d = a.cw[0] + a.vloc[i] - eps;
+        const double p0r = pr[i], p0i = pi[i];
+        // (V - eps - i omega) p: real part d p_r + omega p_i, imaginary part d p_i - omega p_r
+        const double vr = sr + d * p0r + om * p0i;
+        const double vi = si + d * p0i - om * p0r;
+        qr[i] = vr;
+        qi[i] = vi;
+        acc[0] += p0r * vr - p0i * vi;
+        acc[1] += p0r * vi + p0i * vr;
+        acc[2] += p0r * p0r + p0i * p0i;
+        acc[3] += vr * vr + vi * vi;
+    }
+    pc_reduce<4>(acc, red);
+    const double s2 = acc[0] * acc[0] + acc[1] * acc[1];
+    if (!(s2 > a.bd_tol * a.bd_tol * acc[2] * acc[3])) {   // vanishing p^T q: breakdown
+        if (threadIdx.x == 0) {
+            a.iters[s] = it;
+            a.status[s] = 2;
+            a.active[s] = 0;
+        }
+        return;
+    }
+    const double2 rho = a.rho[s];
+    const double ar = (rho.x * acc[0] + rho.y * acc[1]) / s2;
+    const double ai = (rho.y * acc[0] - rho.x * acc[1]) / s2;
+    double* rr = a.r + nd * (2 * int64_t(s));
+    double* ri = rr + nd;
+    double2* xs = a.x + int64_t(s) * nd;
+    double acc2[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < nd; i += PB) {
+        const double p0r = pr[i], p0i = pi[i], q0r = qr[i], q0i = qi[i];
+        double2 xv = xs[i];
+        xv.x += ar * p0r - ai * p0i;
+        xv.y += ar * p0i + ai * p0r;
+        xs[i] = xv;
+        const double nr = rr[i] - (ar * q0r - ai * q0i);
+        const double ni = ri[i] - (ar * q0i + ai * q0r);
+        rr[i] = nr;
+        ri[i] = ni;
+        acc2[0] += nr * nr + ni * ni;
+    }
+    pc_reduce<1>(acc2, red);
+    if (threadIdx.x == 0) {
+        a.iters[s] = it;
+        if (acc2[0] <= a.tol2 * a.b2[s]) {
+            a.active[s] = 0;
+        } else if (it >= a.max_iter) {
+            a.status[s] = 1;
+            a.active[s] = 0;
+        }
+    }
+}
+
+// rho' = r^T z; first: p = z, else p = z + (rho'/rho) p; rho = rho'.
+__global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
+    __shared__ double red[(PB / 64) * 4];
+    const int s = blockIdx.x;
+    if (!a.active[s]) return;
+    const int64_t nd = a.nd;
+    const double* rr = a.r + nd * (2 * int64_t(s));
+    const double* ri = rr + nd;
+    const double* zr = a.z + nd * (2 * int64_t(s));
+    const double* zi = zr + nd;
+    double* pr = a.p + nd * (2 * int64_t(s));
+    double* pi = pr + nd;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // rho' re/im, |r|^2, |z|^2
+    for (int64_t i = threadIdx.x; i < nd; i += PB) {
+        const double a0 = rr[i], a1 = ri[i], c0 = zr[i], c1 = zi[i];
+        acc[0] += a0 * c0 - a1 * c1;
+        acc[1] += a0 * c1 + a1 * c0;
+        acc[2] += a0 * a0 + a1 * a1;
+        acc[3] += c0 * c0 + c1 * c1;
+    }
+    pc_reduce<4>(acc, red);
+    const double n2 = acc[0] * acc[0] + acc[1] * acc[1];
+    if (!(n2 > a.bd_tol * a.bd_tol * acc[2] * acc[3])) {   // vanishing r^T z: breakdown
+        if (threadIdx.x == 0) {
+            a.status[s] = 2;
+            a.active[s] = 0;
+        }
+        return;
+    }
+    double br = 0.0, bi = 0.0;
+    if (!first) {
+        const double2 rho = a.rho[s];
+        const double rr2 = rho.x * rho.x + rho.y * rho.y;
+        br = (acc[0] * rho.x + acc[1] * rho.y) / rr2;
+        bi = (acc[1] * rho.x - acc[0] * rho.y) / rr2;
+    }
+    for (int64_t i = threadIdx.x; i < nd; i += PB) {
+        const double o0 = first ? 0.0 : pr[i], o1 = first ? 0.0 : pi[i];
+        pr[i] = zr[i] + br * o0 - bi * o1;
+        pi[i] = zi[i] + br * o1 + bi * o0;
+    }
+    if (threadIdx.x == 0) a.rho[s] = double2{acc[0], acc[1]};
+}
+
+__global__ __launch_bounds__(PB) void vloc_mean_kernel(int64_t nd, const double* v, double* out) {
+    __shared__ double red[PB / 64];
+    double acc[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < nd; i += PB) acc[0] += v[i];
+    pc_reduce<1>(acc, red);
+    if (threadIdx.x == 0) *out = acc[0] / double(nd);
+}
+
+}  // namespace
+
+hipError_t launch_vloc_mean(int64_t nd, const double* vloc, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(vloc_mean_kernel, dim3(1), dim3(PB), 0, s, nd, vloc, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
+    if (L.nsys <= 0) return hipSuccess;
+    PcArgs a{};
+    a.n0 = L.g.n0;
+    a.n1 = L.g.n1;
+    a.n2 = L.g.n2;
+    a.periodic = L.g.periodic() ? 1 : 0;
+    a.nd = L.g.nd();
+    double w[7];
+    fd_weights(w);
+    const double ih2 = 1.0 / (L.g.h * L.g.h);
+    a.cw[0] = -0.5 * 3.0 * w[0] * ih2;
+    for (int k = 1; k <= 6; ++k) a.cw[k] = -0.5 * w[k] * ih2;
+    a.vloc = L.vloc;
+    a.eps = L.eps;
+    a.omega_v = L.omega_v;
+    a.ns = L.ns;
+    a.tol2 = L.tol * L.tol;
+    a.bd_tol = 1e-14;
+    a.max_iter = L.max_iter;
+    a.r = L.r;
+    a.p = L.p;
+    a.z = L.z;
+    a.q = L.q;
+    a.x = L.x;
+    a.rhs = L.rhs;
+    a.rho = L.rho;
+    a.b2 = L.b2;
+    a.active = L.active;
+    a.iters = L.iters;
+    a.status = L.status;
+    const dim3 grid(unsigned(L.nsys)), block(PB);
+    auto precond = [&]() {
+        return launch_kron_precond(L.g, L.nsys, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky,
+                                   L.kz, L.kshift, s);
+    };
+    hipLaunchKernelGGL(pc_start, grid, block, 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = precond()) != hipSuccess) return e;
+    hipLaunchKernelGGL(pc_rz, grid, block, 0, s, a, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::vector<int> act(L.nsys);
+    for (int it = 1; it <= L.max_iter; ++it) {
+        hipLaunchKernelGGL(pc_step, grid, block, 0, s, a, it);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (it % kCheckEvery == 0 || it == L.max_iter) {
+            if ((e = hipMemcpyAsync(act.data(), L.active, sizeof(int) * L.nsys,
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+            bool any = false;
+            for (int v : act) any = any || v != 0;
+            if (!any) break;
+        }
+        if (it == L.max_iter) break;
+        if ((e = precond()) != hipSuccess) return e;
+        hipLaunchKernelGGL(pc_rz, grid, block, 0, s, a, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace rpa

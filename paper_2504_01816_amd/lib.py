@@ -14,6 +14,7 @@ RPA_OK, RPA_ENOTCONV = 0, 1
 RPA_EINVAL, RPA_EWORKSPACE, RPA_EBREAKDOWN, RPA_ENOTPD, RPA_EHIP, RPA_ENOTIMPL = -1, -2, -3, -4, -5, -6
 RPA_FP64, RPA_MIXED = 0, 1
 RPA_WARM, RPA_INDEPENDENT = 0, 1
+RPA_FLAG_PRECOND = 1
 RPA_BC_PERIODIC, RPA_BC_DIRICHLET = 0, 1
 RPA_OP_COULOMB, RPA_OP_CHI0, RPA_OP_SUBSPACE, RPA_OP_ENERGY, RPA_OP_BACKWARD = 0, 1, 2, 3, 4
 

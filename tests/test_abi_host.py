@@ -159,6 +159,25 @@ def test_chi0_rejects_bad_cells(so, mut, code):
     assert so.rpa_last_error()
 
 
+def test_option_flags_are_validated_on_the_host(so):
+    c = _cell()
+    o = L.default_options(flags=4)                            # unknown bit
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(o), None,
+                             0x5000, 1 << 30, None) == L.RPA_EINVAL
+    o = L.default_options(flags=L.RPA_FLAG_PRECOND, precision=L.RPA_MIXED)
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(o), None,
+                             0x5000, 1 << 30, None) == L.RPA_ENOTIMPL
+    # the preconditioned solver keeps more state per system: a larger workspace
+    nv = (ctypes.c_int32 * 1)(16)
+    plain, pre = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(c), nv, 1, None,
+                                 ctypes.byref(plain)) == 0
+    o = L.default_options(flags=L.RPA_FLAG_PRECOND)
+    assert so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(c), nv, 1, ctypes.byref(o),
+                                 ctypes.byref(pre)) == 0
+    assert pre.value > plain.value + 16 * 4 * 12 ** 3 * 80
+
+
 def test_chi0_rejects_bad_scalars_and_workspace(so):
     c = _cell(eps=[0.0, 1.0, 0.5, 2.0])                     # not ascending
     assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5000, 1 << 30,
