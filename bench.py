@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ec-tol", type=float, default=1e-8)
+    ap.add_argument("--precond", action="store_true",
+                    help="Sternheimer solves by COCG with the Kronecker shifted-Laplacian "
+                         "preconditioner (FP64)")
     ap.add_argument("--max-systems", type=int, default=0,
                     help="cap on COCG systems per launch (0: the library's memory budget)")
     ap.add_argument("--max-subspace", type=int, default=50)
@@ -126,6 +129,7 @@ def main():
     prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
     opts = dict(precision=prec, cocg_tol=wl.cocg_tol, subspace_iters=args.max_subspace,
                 ec_tol=args.ec_tol, sq_order=args.sq_order, max_systems=args.max_systems,
+                flags=L.RPA_FLAG_PRECOND if args.precond else 0,
                 freq_mode=L.RPA_WARM if args.freq_mode == "warm" else L.RPA_INDEPENDENT)
     if wl.subspace_iters > 0:
         opts.update(subspace_iters=wl.subspace_iters, ec_tol=0.0)
@@ -201,7 +205,8 @@ def main():
                    "n_occ": wl.cells[0].n_occ, "n_r": wl.n_r[0], "n_freq": len(wl.omegas),
                    "cocg_tol": wl.cocg_tol, "ec_tol": opts["ec_tol"],
                    "backward": not args.no_backward, "precision": args.precision,
-                   "freq_mode": args.freq_mode, "sq_order": args.sq_order},
+                   "freq_mode": args.freq_mode, "sq_order": args.sq_order,
+                   "precond": bool(args.precond)},
         "time_to_ec_s": float(np.mean([s["fwd_s"] for s in steps])),
         "backward_s": float(np.mean([s["bwd_s"] for s in steps])),
         "E_c": steps[-1]["E"],
@@ -218,9 +223,14 @@ def main():
     }
     if args.compare == "other":
         # the metric's comparison: the same path and inputs in the other precision (complex64
-        # state with float64 reliable updates against complex128)
-        other = "mixed" if args.precision == "fp64" else "fp64"
-        o2 = dict(opts, precision=L.RPA_MIXED if other == "mixed" else L.RPA_FP64)
+        # state with float64 reliable updates against complex128); a preconditioned run is
+        # compared with the plain FP64 solver instead
+        if args.precond:
+            other = "fp64"
+            o2 = dict(opts, flags=0)
+        else:
+            other = "mixed" if args.precision == "fp64" else "fp64"
+            o2 = dict(opts, precision=L.RPA_MIXED if other == "mixed" else L.RPA_FP64)
         step(o2)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -228,7 +238,7 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter() - t
         out["compare"] = {
-            "precision": other,
+            "precision": other, "precond": False,
             "chi0_block_applies_per_s": s2["applies"] / t,
             "time_to_ec_s": s2["fwd_s"], "backward_s": s2["bwd_s"],
             "E_c": s2["E"], "subspace_iters": s2["iters"],
