@@ -7,9 +7,14 @@
 //   rpa_subspace_iter     repeat: u = nu^{1/2} V; D = chi0 u; R = nu^{1/2} D; C = sym(V^T R);
 //                         E = W/(2pi)(ln det(I-C) + tr C); M = R^T R = L L^T; V = R L^{-T}
 //   rpa_apply_chi0        per chunk of trial vectors: projector coefficients, projected
-//                         right-hand sides, batched COCG, Delta rho
+//                         right-hand sides, batched COCG (mixed precision: then the FP64
+//                         continuation of systems stopped at the cap; RPA_FLAG_PRECOND: the
+//                         preconditioned solver instead), Delta rho
 //   rpa_energy_backward   per frequency: eig(C_m), W = V_m Y, u = nu^{1/2} W, COCG with the
 //                         complex solutions kept, gradient accumulation
+// In RPA_INDEPENDENT mode rpa_energy batches the frequencies still iterating into one chi0
+// apply per subspace iteration; several cells run concurrently, one host thread and stream
+// each, in their own workspace slices.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -626,7 +631,7 @@ int precond_setup(const rpa_cell* cell, const Grid& g, const Chi0Buf& b, Chi0Hos
 // systems are launched (the dispatch list is their indices).  Needs the host copy of the
 // statuses from tally().
 int continue_capped(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Buf& b,
-                    int nv, bool x_complex, Chi0Host& h, SolveTally& t, hipStream_t s) {
+                    int nv, Chi0Host& h, SolveTally& t, hipStream_t s) {
     if (!b.mixed) return RPA_OK;
     const int S = cell->n_occ * nv;
     std::vector<int> capped;
@@ -656,7 +661,6 @@ int continue_capped(const rpa_cell* cell, const Grid& g, const Opts& o, const Ch
     L.fp32 = false;
     L.b2 = b.b2;
     L.x_accum = true;
-    (void)x_complex;
     hipEvent_t e0, e1;
     RPA_CHECK(timer_events(&e0, &e1));
     RPA_HIP(hipEventRecord(e0, s));
@@ -693,7 +697,7 @@ int chi0_apply(const rpa_cell* cell, const Grid& g, int nvec, const double* in, 
         const int nv = std::min(b.chunk, nvec - j0);
         RPA_CHECK(solve_chunk(cell, g, o, b, in + nd * j0, j0, nv, false, h, s));
         RPA_CHECK(tally(b, ns * nv, nd, t, h, int64_t(j0) * ns, s));
-        RPA_CHECK(continue_capped(cell, g, o, b, nv, false, h, t, s));
+        RPA_CHECK(continue_capped(cell, g, o, b, nv, h, t, s));
         RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
                             b.x_complex ? 2 : 1, out + nd * j0, s));
     }
@@ -1341,7 +1345,7 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
             const int nv = std::min(b.xb.chunk, nr - j0);
             RPA_CHECK(solve_chunk(cell, g, o, b.xb, b.U + nd * j0, j0, nv, b.xb.x_complex, h, s));
             RPA_CHECK(tally(b.xb, ns * nv, nd, t, h, int64_t(j0) * ns, s));
-            RPA_CHECK(continue_capped(cell, g, o, b.xb, nv, true, h, t, s));
+            RPA_CHECK(continue_capped(cell, g, o, b.xb, nv, h, t, s));
             RPA_HIP(launch_grad_accum_d(nd, ns, nv, cell->psi, b.xb.eps, omega[m], b.xb.coeff,
                                         b.xb.dbuf, b.coefk + j0, b.xb.x, false, grad_vloc, s));
         }
