@@ -524,11 +524,18 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
                                         reinterpret_cast<double*>(b.r), nullptr, s));
     h.om_chunk.assign(h.omega.begin() + j0, h.omega.begin() + j0 + nv);
     if (b.precond) {
+        // slots in dispatch order (longest solve first), so the systems still iterating stay
+        // in a prefix of the slots that the preconditioner passes cover
+        dispatch_order(cell, nv, j0, h);
         RPA_HIP(hipMemcpyAsync(b.omega_v, h.om_chunk.data(), sizeof(double) * nv,
                                hipMemcpyHostToDevice, s));
+        RPA_HIP(hipMemcpyAsync(b.order, h.order.data(), sizeof(int) * ns * nv,
+                               hipMemcpyHostToDevice, s));
         h.kshift.resize(size_t(ns) * nv);
-        for (int i = 0; i < ns * nv; ++i)
-            h.kshift[i] = double2{std::max(h.vmean - cell->eps[i % ns], 0.5), h.om_chunk[i / ns]};
+        for (int t = 0; t < ns * nv; ++t) {
+            const int i = h.order[t];
+            h.kshift[t] = double2{std::max(h.vmean - cell->eps[i % ns], 0.5), h.om_chunk[i / ns]};
+        }
         RPA_HIP(hipMemcpyAsync(b.kshift, h.kshift.data(), sizeof(double2) * ns * nv,
                                hipMemcpyHostToDevice, s));
         PcocgLaunch P{};
@@ -538,6 +545,7 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
         P.vloc = cell->v_loc;
         P.eps = b.eps;
         P.omega_v = b.omega_v;
+        P.order = b.order;
         P.kshift = b.kshift;
         P.tol = o.cocg_tol;
         P.max_iter = o.cocg_max_iter;

@@ -93,7 +93,8 @@ struct PcocgLaunch {
     const double* vloc;
     const double* eps;      // device, ns
     const double* omega_v;  // device, nsys / ns: frequency of trial vector j
-    const double2* kshift;  // device, nsys: (sigma, omega) of each system's preconditioner
+    const int* order;       // device, nsys: slot t solves system order[t] (a permutation)
+    const double2* kshift;  // device, nsys: (sigma, omega) of slot t's preconditioner
     double tol;
     int max_iter;
     const double2* rhs;     // nsys x N_d complex (interleaved): right-hand sides

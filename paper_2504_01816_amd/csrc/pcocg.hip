@@ -18,8 +18,12 @@
 // all systems at once.  Every thread touches the same points in both loops of a kernel, so
 // a value a thread writes is read back only by itself.  Converged systems drop out of the
 // per-system kernels; the host tests for the end every few iterations.
-// Layout: r, p, z, q as N_d x 2 nsys real columns (real, imaginary part of system s in
-// columns 2s, 2s+1); x and the right-hand sides complex interleaved, nsys x N_d.
+// Slots: the systems are placed in slots t = 0 .. nsys-1 in the dispatch order (expected
+// longest solve first), so the systems still iterating gather in a prefix of the slots and
+// the preconditioner passes run on that prefix only.
+// Layout: r, p, z, q as N_d x 2 nsys real columns (real, imaginary part of slot t in columns
+// 2t, 2t+1), rho, b2, active and the preconditioner shifts per slot; x, the right-hand
+// sides, iteration counts and statuses per system, x and b complex interleaved, nsys x N_d.
 #include <vector>
 
 #include "internal.h"
@@ -46,6 +50,7 @@ struct PcArgs {
     double2* rho;
     double* b2;
     int *active, *iters, *status;
+    const int* order;   // slot t holds system order[t]
 };
 
 // Sum of NV values over the workgroup, in a fixed order (wave butterfly, then waves in order);
@@ -70,12 +75,12 @@ __device__ void pc_reduce(double (&v)[NV], double* red) {
 // r = b (split), x = 0, |b|^2; systems with b = 0 are done (x = 0).
 __global__ __launch_bounds__(PB) void pc_start(PcArgs a) {
     __shared__ double red[(PB / 64) * 1];
-    const int s = blockIdx.x;
+    const int s = blockIdx.x, sys = a.order[s];
     const int64_t nd = a.nd;
-    const double2* b = a.rhs + int64_t(s) * nd;
+    const double2* b = a.rhs + int64_t(sys) * nd;
     double* rr = a.r + nd * (2 * int64_t(s));
     double* ri = rr + nd;
-    double2* x = a.x + int64_t(s) * nd;
+    double2* x = a.x + int64_t(sys) * nd;
     double acc[1] = {0.0};
     for (int64_t i = threadIdx.x; i < nd; i += PB) {
         const double2 v = b[i];
@@ -88,8 +93,8 @@ __global__ __launch_bounds__(PB) void pc_start(PcArgs a) {
     if (threadIdx.x == 0) {
         a.b2[s] = acc[0];
         a.active[s] = acc[0] > 0.0 ? 1 : 0;
-        a.iters[s] = 0;
-        a.status[s] = 0;
+        a.iters[sys] = 0;
+        a.status[sys] = 0;
     }
 }
 
@@ -114,8 +119,9 @@ __global__ __launch_bounds__(PB) void pc_step(PcArgs a, int it) {
     __shared__ double red[(PB / 64) * 4];
     const int s = blockIdx.x;
     if (!a.active[s]) return;
+    const int sys = a.order[s];
     const int64_t nd = a.nd;
-    const double eps = a.eps[s % a.ns], om = a.omega_v[s / a.ns];
+    const double eps = a.eps[sys % a.ns], om = a.omega_v[sys / a.ns];
     const double* pr = a.p + nd * (2 * int64_t(s));
     const double* pi = pr + nd;
     double* qr = a.q + nd * (2 * int64_t(s));
@@ -150,8 +156,8 @@ __global__ __launch_bounds__(PB) void pc_step(PcArgs a, int it) {
     const double s2 = acc[0] * acc[0] + acc[1] * acc[1];
     if (!(s2 > a.bd_tol * a.bd_tol * acc[2] * acc[3])) {   // vanishing p^T q: breakdown
         if (threadIdx.x == 0) {
-            a.iters[s] = it;
-            a.status[s] = 2;
+            a.iters[sys] = it;
+            a.status[sys] = 2;
             a.active[s] = 0;
         }
         return;
@@ -161,7 +167,7 @@ __global__ __launch_bounds__(PB) void pc_step(PcArgs a, int it) {
     const double ai = (rho.y * acc[0] - rho.x * acc[1]) / s2;
     double* rr = a.r + nd * (2 * int64_t(s));
     double* ri = rr + nd;
-    double2* xs = a.x + int64_t(s) * nd;
+    double2* xs = a.x + int64_t(sys) * nd;
     double acc2[1] = {0.0};
     for (int64_t i = threadIdx.x; i < nd; i += PB) {
         const double p0r = pr[i], p0i = pi[i], q0r = qr[i], q0i = qi[i];
@@ -177,11 +183,11 @@ __global__ __launch_bounds__(PB) void pc_step(PcArgs a, int it) {
     }
     pc_reduce<1>(acc2, red);
     if (threadIdx.x == 0) {
-        a.iters[s] = it;
+        a.iters[sys] = it;
         if (acc2[0] <= a.tol2 * a.b2[s]) {
             a.active[s] = 0;
         } else if (it >= a.max_iter) {
-            a.status[s] = 1;
+            a.status[sys] = 1;
             a.active[s] = 0;
         }
     }
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
     const double n2 = acc[0] * acc[0] + acc[1] * acc[1];
     if (!(n2 > a.bd_tol * a.bd_tol * acc[2] * acc[3])) {   // vanishing r^T z: breakdown
         if (threadIdx.x == 0) {
-            a.status[s] = 2;
+            a.status[a.order[s]] = 2;
             a.active[s] = 0;
         }
         return;
@@ -277,9 +283,11 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
     a.active = L.active;
     a.iters = L.iters;
     a.status = L.status;
+    a.order = L.order;
     const dim3 grid(unsigned(L.nsys)), block(PB);
+    int prefix = L.nsys;   // slots 0 .. prefix-1 hold every system still iterating
     auto precond = [&]() {
-        return launch_kron_precond(L.g, L.nsys, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky,
+        return launch_kron_precond(L.g, prefix, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky,
                                    L.kz, L.kshift, s);
     };
     hipLaunchKernelGGL(pc_start, grid, block, 0, s, a);
@@ -297,9 +305,10 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
                                     hipMemcpyDeviceToHost, s)) != hipSuccess)
                 return e;
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-            bool any = false;
-            for (int v : act) any = any || v != 0;
-            if (!any) break;
+            prefix = 0;
+            for (int t = 0; t < L.nsys; ++t)
+                if (act[t]) prefix = t + 1;
+            if (prefix == 0) break;
         }
         if (it == L.max_iter) break;
         if ((e = precond()) != hipSuccess) return e;
