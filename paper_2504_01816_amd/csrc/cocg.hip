@@ -146,9 +146,10 @@ Chosen choose(const Grid& g, bool mixed, bool xcomplex, bool allow_forced) {
             if (lds > 150 * 1024) continue;
             const double idle = double(bs * v.C - ps) / double(bs * v.C);
             // halo rows re-read per slab: 12 / rows extra reads of the swept vector
-            const double halo = v.slab ? 0.5 * 12.0 / rows : 0.0;
-            // spills: a fixed penalty plus one growing with the spilled bytes per lane
-            const double spill = scratch > 0 ? 1.0 + double(scratch) / 1024.0 : 0.0;
+            const double halo = v.slab ? 12.0 / rows : 0.0;
+            // spills, by spilled bytes per lane: a few dozen spilled registers cost less than
+            // the halo re-reads of a slab split (measured at 28^3 and 32^3), hundreds far more
+            const double spill = double(scratch) / 256.0;
             double cost = idle + halo + spill + 0.03 * (4 - v.Z) + 0.05 * (2 - nbuf);
             if (cost < best_cost - 1e-12) {
                 best_cost = cost;
