@@ -94,3 +94,38 @@ def test_slab_energy_and_backward_match_oracle(periodic, monkeypatch, capfd):
     gref = ograd.energy_backward(c.vloc, c.psi.T, c.eps, c.shape, c.h, om, W, Vs, Cs, 1e-12, 5000)
     assert rc == 0 and rel(grad.cpu().numpy(), gref) < 1e-8
     assert "nslab=3" in capfd.readouterr().err
+
+
+def test_slab_mixed_capped_systems_continue_in_fp64(periodic, monkeypatch, capfd):
+    # complex64 stage capped below what its slowest systems need, in slab mode: the FP64
+    # continuation runs through the slab kernel as well
+    c, dc = periodic
+    say("slab mixed with a low cap: FP64 continuation")
+    forced(monkeypatch, "1,1,512,0,0,2")
+    U = np.random.default_rng(8).standard_normal((3, c.nd))
+    ref, iters, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, 0.05, c.shape, c.h, 1e-10,
+                                     5000)
+    cap = int(1.25 * iters.max())       # FP64 from scratch fits; the complex64 stage does not
+    out, rc, st = api.rpa_apply_chi0(dc, 0.05, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-10, cocg_max_iter=cap, precision=1))
+    say("cap", cap, "fallbacks", st["fp64_fallbacks"], "unconverged", st["n_unconverged"])
+    assert rc == 0 and st["n_unconverged"] == 0
+    # two solutions meeting tol 1e-10 differ by up to cond(A) tol at this frequency
+    assert rel(out.cpu().numpy().T, ref) < 5e-8
+    assert "nslab=2" in capfd.readouterr().err
+
+
+def test_slab_preconditioned_solver_on_the_same_cell(periodic):
+    # the preconditioned solver on a non-cubic periodic cell (three different 1D bases)
+    c, dc = periodic
+    say("preconditioned chi0 on the 16x36x12 cell, two chunks")
+    from oracle import precond as opre
+    U = np.random.default_rng(9).standard_normal((4, c.nd))
+    out, rc, st = api.rpa_apply_chi0(dc, 0.3, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-12, flags=1, max_systems=8))
+    ref, it_ref, _ = opre.chi0_apply_precond(U.T, c.vloc, c.psi.T, c.eps, 0.3, c.shape, c.h,
+                                             1e-12, 5000)
+    assert rc == 0 and st["cocg_systems"] == 16
+    assert rel(out.cpu().numpy().T, ref) < 1e-9
+    assert abs(st["cocg_iters_total"] - int(it_ref.sum())) <= it_ref.size
+
