@@ -14,8 +14,9 @@
 // fit the register-resident z-march of the plain COCG kernel, so each iteration is a few
 // batched launches driven by the host: pc_step and pc_rz run one workgroup per system (the
 // stencil gathers its 36 neighbours through the caches, reductions are workgroup-local and
-// in a fixed order), and z = M r is 3 + 3 Kronecker GEMM passes with a diagonal scale over
-// all systems at once.  Every thread touches the same points in both loops of a kernel, so
+// in a fixed order), and z = M r is three LDS-staged passes (x-y planes forward, z pencils
+// with the diagonal scale, x-y planes inverse) over all systems at once, or for larger grids
+// 3 + 3 Kronecker GEMM passes with a diagonal scale.  Every thread touches the same points in both loops of a kernel, so
 // a value a thread writes is read back only by itself.  Converged systems drop out of the
 // per-system kernels; the host tests for the end every few iterations.
 // Slots: the systems are placed in slots t = 0 .. nsys-1 in the dispatch order (expected
@@ -237,6 +238,134 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
     if (threadIdx.x == 0) a.rho[s] = double2{acc[0], acc[1]};
 }
 
+// ------------------------------------------------------------------ fused preconditioner
+// z = K^{-1} r in three passes instead of six GEMM passes and a scale pass: forward x and y
+// transforms of one z-plane of one system in LDS; forward z transform, diagonal scale and
+// inverse z transform of 64 z-pencils in LDS (results of the forward transform in
+// registers); inverse y and x transforms per plane.  Used for n0, n1 <= 48 and n2 <= 64.
+constexpr int kFusedMaxXY = 48;
+constexpr int kFusedMaxZ = 64;
+constexpr int kPencils = 64;
+constexpr int kZr = kFusedMaxZ / (PB / kPencils);   // z values per thread in the pencil pass
+
+// forward (INV = false): c_(a,b) = sum_(x,y) Ux[x + n0 a] Uy[y + n1 b] f_(x,y); inverse: the
+// transposed bases.  grid (n2, systems), in/out: N_d x 2 nsys split columns.
+template <bool INV>
+__global__ __launch_bounds__(PB) void pc_xy(const double* in, double* out, int n0, int n1,
+                                            int64_t nd, const double* Ux, const double* Uy) {
+    extern __shared__ double2 shx[];
+    const int P = n0 * n1;
+    const int z = blockIdx.x, t = blockIdx.y;
+    double2* A = shx;
+    double2* B = shx + P;
+    double* ux = reinterpret_cast<double*>(shx + 2 * P);
+    double* uy = ux + n0 * n0;
+    const double* ir = in + nd * (2 * int64_t(t)) + int64_t(z) * P;
+    const double* ii = ir + nd;
+    for (int i = threadIdx.x; i < P; i += PB) A[i] = double2{ir[i], ii[i]};
+    for (int i = threadIdx.x; i < n0 * n0; i += PB) ux[i] = Ux[i];
+    for (int i = threadIdx.x; i < n1 * n1; i += PB) uy[i] = Uy[i];
+    __syncthreads();
+    for (int o = threadIdx.x; o < P; o += PB) {          // along x
+        const int y = o / n0, a = o - y * n0;
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < n0; ++k) {
+            const double u = INV ? ux[a + n0 * k] : ux[k + n0 * a];
+            const double2 v = A[y * n0 + k];
+            sr += u * v.x;
+            si += u * v.y;
+        }
+        B[o] = double2{sr, si};
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < P; o += PB) {          // along y
+        const int b = o / n0, x = o - b * n0;
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < n1; ++k) {
+            const double u = INV ? uy[b + n1 * k] : uy[k + n1 * b];
+            const double2 v = B[k * n0 + x];
+            sr += u * v.x;
+            si += u * v.y;
+        }
+        A[o] = double2{sr, si};
+    }
+    __syncthreads();
+    double* orr = out + nd * (2 * int64_t(t)) + int64_t(z) * P;
+    double* oi = orr + nd;
+    for (int i = threadIdx.x; i < P; i += PB) {
+        orr[i] = A[i].x;
+        oi[i] = A[i].y;
+    }
+}
+
+// In place on the x-y mode coefficients: forward z transform, division by
+// 1/2 (kx + ky + kz) + sigma_t - i omega_t, inverse z transform.  grid (ceil(P/64), systems).
+__global__ __launch_bounds__(PB) void pc_zscale(double* data, int n0, int n1, int n2, int64_t nd,
+                                                const double* Uz, const double* kx,
+                                                const double* ky, const double* kz,
+                                                const double2* kshift) {
+    extern __shared__ double2 shz[];
+    const int P = n0 * n1;
+    const int g0 = blockIdx.x * kPencils, t = blockIdx.y;
+    const int j = threadIdx.x % kPencils, cg = threadIdx.x / kPencils, ng = PB / kPencils;
+    double2* Pz = shz;                                          // n2 x 64
+    double* uz = reinterpret_cast<double*>(shz + n2 * kPencils);
+    double* dr = data + nd * (2 * int64_t(t));
+    double* di = dr + nd;
+    for (int e = threadIdx.x; e < n2 * kPencils; e += PB) {
+        const int zz = e / kPencils, xy = g0 + (e - zz * kPencils);
+        Pz[e] = (xy < P) ? double2{dr[xy + int64_t(P) * zz], di[xy + int64_t(P) * zz]}
+                         : double2{0.0, 0.0};
+    }
+    for (int i = threadIdx.x; i < n2 * n2; i += PB) uz[i] = Uz[i];
+    __syncthreads();
+    double2 acc[kZr];
+#pragma unroll
+    for (int k = 0; k < kZr; ++k) {
+        const int c = cg + ng * k;
+        double sr = 0.0, si = 0.0;
+        if (c < n2) {
+            for (int zz = 0; zz < n2; ++zz) {
+                const double u = uz[zz + n2 * c];
+                const double2 v = Pz[zz * kPencils + j];
+                sr += u * v.x;
+                si += u * v.y;
+            }
+        }
+        acc[k] = double2{sr, si};
+    }
+    __syncthreads();                                            // every read of Pz done
+    const int xy = g0 + j;
+    const int a = xy % n0, b = (xy / n0) % n1;
+    const double2 ks = kshift[t];
+#pragma unroll
+    for (int k = 0; k < kZr; ++k) {
+        const int c = cg + ng * k;
+        if (c < n2) {
+            const double d = 0.5 * (kx[a] + ky[b] + kz[c]) + ks.x, w = ks.y;
+            const double den = 1.0 / (d * d + w * w);
+            const double2 v = acc[k];
+            Pz[c * kPencils + j] = double2{(v.x * d - v.y * w) * den, (v.y * d + v.x * w) * den};
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < kZr; ++k) {
+        const int zz = cg + ng * k;
+        if (zz >= n2) break;
+        double sr = 0.0, si = 0.0;
+        for (int c = 0; c < n2; ++c) {
+            const double u = uz[zz + n2 * c];
+            const double2 v = Pz[c * kPencils + j];
+            sr += u * v.x;
+            si += u * v.y;
+        }
+        if (xy < P) {
+            dr[xy + int64_t(P) * zz] = sr;
+            di[xy + int64_t(P) * zz] = si;
+        }
+    }
+}
+
 __global__ __launch_bounds__(PB) void vloc_mean_kernel(int64_t nd, const double* v, double* out) {
     __shared__ double red[PB / 64];
     double acc[1] = {0.0};
@@ -249,6 +378,40 @@ __global__ __launch_bounds__(PB) void vloc_mean_kernel(int64_t nd, const double*
 
 hipError_t launch_vloc_mean(int64_t nd, const double* vloc, double* out, hipStream_t s) {
     hipLaunchKernelGGL(vloc_mean_kernel, dim3(1), dim3(PB), 0, s, nd, vloc, out);
+    return hipGetLastError();
+}
+
+// z = K^{-1} r on the first nsys slots: the fused passes where the grid allows, else the
+// Kronecker GEMM passes.
+hipError_t apply_precond(const PcocgLaunch& L, int nsys, hipStream_t s) {
+    const Grid& g = L.g;
+    if (g.n0 > kFusedMaxXY || g.n1 > kFusedMaxXY || g.n2 > kFusedMaxZ || nsys > 65535)
+        return launch_kron_precond(g, nsys, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky, L.kz,
+                                   L.kshift, s);
+    const int P = g.n0 * g.n1;
+    const int64_t nd = g.nd();
+    const size_t lxy = size_t(2 * P) * sizeof(double2) +
+                       size_t(g.n0 * g.n0 + g.n1 * g.n1) * sizeof(double);
+    const size_t lz = size_t(g.n2 * kPencils) * sizeof(double2) + size_t(g.n2 * g.n2) * sizeof(double);
+    hipError_t e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(pc_xy<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lxy))) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(pc_xy<true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lxy))) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(pc_zscale),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lz))) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(pc_xy<false>, dim3(unsigned(g.n2), unsigned(nsys)), dim3(PB), lxy, s, L.r,
+                       L.tmp, g.n0, g.n1, nd, L.Ux, L.Uy);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(pc_zscale, dim3(unsigned((P + kPencils - 1) / kPencils), unsigned(nsys)),
+                       dim3(PB), lz, s, L.tmp, g.n0, g.n1, g.n2, nd, L.Uz, L.kx, L.ky, L.kz,
+                       L.kshift);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(pc_xy<true>, dim3(unsigned(g.n2), unsigned(nsys)), dim3(PB), lxy, s, L.tmp,
+                       L.z, g.n0, g.n1, nd, L.Ux, L.Uy);
     return hipGetLastError();
 }
 
@@ -286,10 +449,7 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
     a.order = L.order;
     const dim3 grid(unsigned(L.nsys)), block(PB);
     int prefix = L.nsys;   // slots 0 .. prefix-1 hold every system still iterating
-    auto precond = [&]() {
-        return launch_kron_precond(L.g, prefix, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky,
-                                   L.kz, L.kshift, s);
-    };
+    auto precond = [&]() { return apply_precond(L, prefix, s); };
     hipLaunchKernelGGL(pc_start, grid, block, 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
