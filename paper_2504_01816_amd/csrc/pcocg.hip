@@ -27,6 +27,7 @@
 // sides, iteration counts and statuses per system, x and b complex interleaved, nsys x N_d.
 #include <vector>
 
+#include "cocg_kernel.h"
 #include "internal.h"
 
 namespace rpa {
@@ -366,6 +367,165 @@ __global__ __launch_bounds__(PB) void pc_zscale(double* data, int n0, int n1, in
     }
 }
 
+// ------------------------------------------------------------------ staged step
+// pc_step on the plain COCG kernel's z-march (register queue along z, LDS-staged planes, row
+// slabs for large planes): q = A p in one sweep over the system, then the pointwise x and r
+// updates over the thread's own columns.  One workgroup per slot.
+struct LeadSplit {   // the swept vector p, from its real and imaginary columns
+    using Buf = double2;
+    const double* pr; const double* pi; int P; const int* col;
+    __device__ Buf load(int z, int i, bool) const { return load_at(z, unsigned(col[i])); }
+    __device__ Buf load_at(int z, unsigned gcol) const {
+        const unsigned idx = unsigned(z * P) + gcol;
+        return double2{pr[idx], pi[idx]};
+    }
+    __device__ double2 make(const Buf& b) const { return b; }
+};
+struct CentQ {       // stores q = A p, accumulates p^T q, |p|^2, |q|^2
+    using Buf = cocg::Empty;
+    double* qr; double* qi; int P; const int* col;
+    double acc[4];
+    __device__ Buf load(int, int) const { return Buf{}; }
+    __device__ void finish(const Buf&, int z, int i, double2 c, double2 q) {
+        const unsigned idx = unsigned(z * P + col[i]);
+        qr[idx] = q.x;
+        qi[idx] = q.y;
+        acc[0] += c.x * q.x - c.y * q.y;
+        acc[1] += c.x * q.y + c.y * q.x;
+        acc[2] += c.x * c.x + c.y * c.y;
+        acc[3] += q.x * q.x + q.y * q.y;
+    }
+};
+
+template <int BSMAX, bool SLAB>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, BSMAX)))
+void pc_step_wg(PcArgs pa, cocg::Args ca, int it) {
+    const int s = blockIdx.x;
+    if (!pa.active[s]) return;
+    const int sys = pa.order[s];
+    cocg::Args a = ca;
+    a.omega = pa.omega_v[sys / pa.ns];
+    const double eps_n = pa.eps[sys % pa.ns];
+    const int tid = threadIdx.x, BS = blockDim.x;
+    const int64_t nd = pa.nd;
+    extern __shared__ __align__(16) unsigned char smem_pc[];
+    double* red = reinterpret_cast<double*>(smem_pc);                  // 16 waves x 8
+    double2* planes = reinterpret_cast<double2*>(smem_pc + 16 * 8 * sizeof(double));
+    const int nslab = SLAB ? a.nslab : 1;
+    cocg::Cols<1> cl;
+    cocg::make_cols<1>(a, 0, tid, BS, cl);
+    if (!a.periodic) {
+        // isolated box: ghost entries read zero (as in the plain kernel)
+        const int nent = a.nbuf * (a.rows + 12) * a.rs;
+        for (int e = tid; e < nent; e += BS) planes[e] = double2{0.0, 0.0};
+        cocg::lds_barrier();
+    }
+    const double* pr = pa.p + nd * (2 * int64_t(s));
+    const double* pi = pr + nd;
+    double* qr = pa.q + nd * (2 * int64_t(s));
+    double* qi = qr + nd;
+    LeadSplit lead{pr, pi, a.P, cl.col};
+    CentQ cent{qr, qi, a.P, cl.col, {0.0, 0.0, 0.0, 0.0}};
+    double2 Q[13][1];
+    for (int sl = 0; sl < nslab; ++sl) {
+        if (SLAB) {
+            cocg::make_cols<1>(a, sl, tid, BS, cl);
+            if (sl > 0) cocg::lds_barrier();
+        }
+        cocg::march<double, double2, 1, 1, SLAB>(a, cl, planes, eps_n, lead, cent, Q, false);
+    }
+    cocg::wg_reduce<4>(cent.acc, red);
+    const double s2 = cent.acc[0] * cent.acc[0] + cent.acc[1] * cent.acc[1];
+    if (!(s2 > pa.bd_tol * pa.bd_tol * cent.acc[2] * cent.acc[3])) {   // breakdown
+        if (tid == 0) {
+            pa.iters[sys] = it;
+            pa.status[sys] = 2;
+            pa.active[s] = 0;
+        }
+        return;
+    }
+    const double2 rho = pa.rho[s];
+    const double ar = cocg::uniform((rho.x * cent.acc[0] + rho.y * cent.acc[1]) / s2);
+    const double ai = cocg::uniform((rho.y * cent.acc[0] - rho.x * cent.acc[1]) / s2);
+    double* rr = pa.r + nd * (2 * int64_t(s));
+    double* ri = rr + nd;
+    double2* xs = pa.x + int64_t(sys) * nd;
+    double acc2[1] = {0.0};
+    // each thread updates the columns it staged in the sweep (same slab and column mapping),
+    // so it reads back only q values it wrote itself
+    for (int sl = 0; sl < nslab; ++sl) {
+        if (SLAB) cocg::make_cols<1>(a, sl, tid, BS, cl);
+        if (!cl.valid[0]) continue;
+        for (int z = 0; z < a.n2; ++z) {
+            const int64_t i = int64_t(z) * a.P + cl.col[0];
+            const double p0r = pr[i], p0i = pi[i], q0r = qr[i], q0i = qi[i];
+            double2 xv = xs[i];
+            xv.x += ar * p0r - ai * p0i;
+            xv.y += ar * p0i + ai * p0r;
+            xs[i] = xv;
+            const double nr = rr[i] - (ar * q0r - ai * q0i);
+            const double ni = ri[i] - (ar * q0i + ai * q0r);
+            rr[i] = nr;
+            ri[i] = ni;
+            acc2[0] += nr * nr + ni * ni;
+        }
+    }
+    cocg::wg_reduce<1>(acc2, red);
+    if (tid == 0) {
+        pa.iters[sys] = it;
+        if (acc2[0] <= pa.tol2 * pa.b2[s]) {
+            pa.active[s] = 0;
+        } else if (it >= pa.max_iter) {
+            pa.status[sys] = 1;
+            pa.active[s] = 0;
+        }
+    }
+}
+
+// Launch shape of the staged step: the whole plane with one column per thread when it fits
+// 1024 threads, else row slabs of >= 12 rows (as the plain kernel).  Returns false when
+// neither fits (the gathered pc_step is used then).
+struct StagedShape {
+    void (*fn)(PcArgs, cocg::Args, int) = nullptr;
+    int bs = 0, nslab = 1, rows = 0, nbuf = 2;
+    size_t lds = 0;
+};
+
+int pc_lds_row(int n0) { return (n0 + 12 + 7) / 8 * 8; }
+
+bool staged_shape(const Grid& g, StagedShape& sh) {
+    const int rs = pc_lds_row(g.n0);
+    for (int nslab = 1; nslab <= g.n1 / 12 || nslab == 1; ++nslab) {
+        if (g.n1 % nslab != 0) continue;
+        const int rows = g.n1 / nslab;
+        if (nslab > 1 && rows < 12) break;
+        const int bs = (rows * g.n0 + 63) / 64 * 64;
+        if (bs > 1024) continue;
+        if (nslab > 1 && 12 * g.n0 > bs) continue;
+        const int bm = bs <= 512 ? 512 : (bs <= 768 ? 768 : 1024);
+        int nbuf = 2;
+        size_t lds = 16 * 8 * sizeof(double) + size_t(nbuf) * (rows + 12) * rs * 16;
+        if (lds > 150 * 1024) {
+            nbuf = 1;
+            lds = 16 * 8 * sizeof(double) + size_t(rows + 12) * rs * 16;
+        }
+        if (lds > 150 * 1024) continue;
+        if (nslab == 1)
+            sh.fn = bm == 512 ? pc_step_wg<512, false> : bm == 768 ? pc_step_wg<768, false>
+                                                                   : pc_step_wg<1024, false>;
+        else
+            sh.fn = bm == 512 ? pc_step_wg<512, true> : bm == 768 ? pc_step_wg<768, true>
+                                                                  : pc_step_wg<1024, true>;
+        sh.bs = bs;
+        sh.nslab = nslab;
+        sh.rows = rows;
+        sh.nbuf = nbuf;
+        sh.lds = lds;
+        return true;
+    }
+    return false;
+}
+
 __global__ __launch_bounds__(PB) void vloc_mean_kernel(int64_t nd, const double* v, double* out) {
     __shared__ double red[PB / 64];
     double acc[1] = {0.0};
@@ -449,6 +609,35 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
     a.order = L.order;
     const dim3 grid(unsigned(L.nsys)), block(PB);
     int prefix = L.nsys;   // slots 0 .. prefix-1 hold every system still iterating
+    // the staged step (the plain kernel's z-march) where a shape fits, else the gathered one
+    StagedShape sh;
+    const bool staged = L.g.n2 >= 12 && staged_shape(L.g, sh);
+    cocg::Args ca{};
+    if (staged) {
+        ca.n0 = L.g.n0;
+        ca.n1 = L.g.n1;
+        ca.n2 = L.g.n2;
+        ca.P = L.g.n0 * L.g.n1;
+        for (int k = 0; k < 7; ++k) ca.cw[k] = a.cw[k];
+        ca.vloc = L.vloc;
+        ca.nd = L.g.nd();
+        ca.nbuf = sh.nbuf;
+        ca.rs = pc_lds_row(L.g.n0);
+        ca.periodic = a.periodic;
+        ca.nslab = sh.nslab;
+        ca.rows = sh.rows;
+        hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(sh.fn),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            int(sh.lds));
+        if (e0 != hipSuccess) return e0;
+    }
+    auto step = [&](int it) {
+        if (staged)
+            hipLaunchKernelGGL(sh.fn, grid, dim3(unsigned(sh.bs)), sh.lds, s, a, ca, it);
+        else
+            hipLaunchKernelGGL(pc_step, grid, block, 0, s, a, it);
+        return hipGetLastError();
+    };
     auto precond = [&]() { return apply_precond(L, prefix, s); };
     hipLaunchKernelGGL(pc_start, grid, block, 0, s, a);
     hipError_t e = hipGetLastError();
@@ -458,8 +647,7 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::vector<int> act(L.nsys);
     for (int it = 1; it <= L.max_iter; ++it) {
-        hipLaunchKernelGGL(pc_step, grid, block, 0, s, a, it);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = step(it)) != hipSuccess) return e;
         if (it % kCheckEvery == 0 || it == L.max_iter) {
             if ((e = hipMemcpyAsync(act.data(), L.active, sizeof(int) * L.nsys,
                                     hipMemcpyDeviceToHost, s)) != hipSuccess)
