@@ -25,6 +25,8 @@
 // Layout: r, p, z, q as N_d x 2 nsys real columns (real, imaginary part of slot t in columns
 // 2t, 2t+1), rho, b2, active and the preconditioner shifts per slot; x, the right-hand
 // sides, iteration counts and statuses per system, x and b complex interleaved, nsys x N_d.
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "cocg_kernel.h"
@@ -243,11 +245,13 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
 // z = K^{-1} r in three passes instead of six GEMM passes and a scale pass: forward x and y
 // transforms of one z-plane of one system in LDS; forward z transform, diagonal scale and
 // inverse z transform of 64 z-pencils in LDS (results of the forward transform in
-// registers); inverse y and x transforms per plane.  Used for n0, n1 <= 48 and n2 <= 64.
-constexpr int kFusedMaxXY = 48;
-constexpr int kFusedMaxZ = 64;
+// registers); inverse y and x transforms per plane.  The dense 1D transforms cost n LDS
+// multiply-adds per point and axis, so the fused passes beat the MFMA GEMM passes only for
+// short axes (measured: 1.25x faster at 24^3, 2.5x slower at 48^3); used for n0, n1, n2 <= 32.
+constexpr int kFusedMaxXY = 32;
+constexpr int kFusedMaxZ = 32;
 constexpr int kPencils = 64;
-constexpr int kZr = kFusedMaxZ / (PB / kPencils);   // z values per thread in the pencil pass
+constexpr int kZr = 64 / (PB / kPencils);   // z values per thread in the pencil pass (n2 <= 64)
 
 // forward (INV = false): c_(a,b) = sum_(x,y) Ux[x + n0 a] Uy[y + n1 b] f_(x,y); inverse: the
 // transposed bases.  grid (n2, systems), in/out: N_d x 2 nsys split columns.
@@ -545,7 +549,12 @@ hipError_t launch_vloc_mean(int64_t nd, const double* vloc, double* out, hipStre
 // Kronecker GEMM passes.
 hipError_t apply_precond(const PcocgLaunch& L, int nsys, hipStream_t s) {
     const Grid& g = L.g;
-    if (g.n0 > kFusedMaxXY || g.n1 > kFusedMaxXY || g.n2 > kFusedMaxZ || nsys > 65535)
+    // RPA_PRECOND_PASSES=gemm forces the GEMM passes (for measurements)
+    static const char* force = std::getenv("RPA_PRECOND_PASSES");
+    const bool fits = g.n0 <= kFusedMaxXY && g.n1 <= kFusedMaxXY && g.n2 <= kFusedMaxZ &&
+                      nsys <= 65535;
+    const bool gemm = !fits || (force && std::strcmp(force, "gemm") == 0);
+    if (gemm)
         return launch_kron_precond(g, nsys, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky, L.kz,
                                    L.kshift, s);
     const int P = g.n0 * g.n1;
