@@ -12,12 +12,14 @@
 //
 // Design: the preconditioner needs whole-vector transforms along every axis, which do not
 // fit the register-resident z-march of the plain COCG kernel, so each iteration is a few
-// batched launches driven by the host: pc_step and pc_rz run one workgroup per system (the
-// stencil gathers its 36 neighbours through the caches, reductions are workgroup-local and
-// in a fixed order), and z = M r is three LDS-staged passes (x-y planes forward, z pencils
-// with the diagonal scale, x-y planes inverse) over all systems at once, or for larger grids
-// 3 + 3 Kronecker GEMM passes with a diagonal scale.  Every thread touches the same points in both loops of a kernel, so
-// a value a thread writes is read back only by itself.  Converged systems drop out of the
+// batched launches driven by the host: the step q = A p with the x and r updates runs one
+// workgroup per system on the plain kernel's z-march (pc_step_wg; pc_step, which gathers
+// the 36 neighbours through the caches, where no march shape fits); pc_rz does r^T z and the
+// p update; reductions are workgroup-local and in a fixed order.  z = M r is three
+// LDS-staged passes (x-y planes forward, z pencils with the diagonal scale, x-y planes
+// inverse) over all systems at once for short axes, else 3 + 3 Kronecker GEMM passes with a
+// diagonal scale.  Every thread touches the same points in both loops of a kernel, so a
+// value a thread writes is read back only by itself.  Converged systems drop out of the
 // per-system kernels; the host tests for the end every few iterations.
 // Slots: the systems are placed in slots t = 0 .. nsys-1 in the dispatch order (expected
 // longest solve first), so the systems still iterating gather in a prefix of the slots and
