@@ -270,14 +270,19 @@ __global__ __launch_bounds__(PB) void pc_xy(const double* in, double* out, int n
     const double* ir = in + nd * (2 * int64_t(t)) + int64_t(z) * P;
     const double* ii = ir + nd;
     for (int i = threadIdx.x; i < P; i += PB) A[i] = double2{ir[i], ii[i]};
-    for (int i = threadIdx.x; i < n0 * n0; i += PB) ux[i] = Ux[i];
+    // x basis stored so that lanes (consecutive a) read consecutive entries: ux[a + n0 k] =
+    // U[a + n0 k] for the inverse, U[k + n0 a] (the transpose) for the forward transform
+    for (int i = threadIdx.x; i < n0 * n0; i += PB) {
+        const int a = i % n0, k = i / n0;
+        ux[i] = INV ? Ux[i] : Ux[k + n0 * a];
+    }
     for (int i = threadIdx.x; i < n1 * n1; i += PB) uy[i] = Uy[i];
     __syncthreads();
     for (int o = threadIdx.x; o < P; o += PB) {          // along x
         const int y = o / n0, a = o - y * n0;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < n0; ++k) {
-            const double u = INV ? ux[a + n0 * k] : ux[k + n0 * a];
+            const double u = ux[a + n0 * k];
             const double2 v = A[y * n0 + k];
             sr += u * v.x;
             si += u * v.y;
