@@ -23,4 +23,6 @@ subspace    Rayleigh-Ritz energy, Cholesky orthonormalisation, subspace iteratio
 quadrature  Gauss-Legendre frequency rule mapped to [0, inf) (Sec. 3)
 energy      full E_c over frequencies (Eq. 10, Algorithm 1)
 gradient    dE_c/dV_loc with orbitals, eigenvalues and saved subspaces fixed
+precond     Kronecker shifted-Laplacian preconditioner and preconditioned COCG (Sec. 3)
+block       block COCG over the trial vectors that share one Sternheimer matrix (Sec. 3)
 """
