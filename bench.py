@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--precond", action="store_true",
                     help="Sternheimer solves by COCG with the Kronecker shifted-Laplacian "
                          "preconditioner (FP64)")
+    ap.add_argument("--block", type=int, default=0,
+                    help="block COCG width (2..8; 0: single systems), with --precond "
+                         "preconditioned (FP64)")
     ap.add_argument("--max-systems", type=int, default=0,
                     help="cap on COCG systems per launch (0: the library's memory budget)")
     ap.add_argument("--max-subspace", type=int, default=50)
@@ -129,7 +132,7 @@ def main():
     prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
     opts = dict(precision=prec, cocg_tol=wl.cocg_tol, subspace_iters=args.max_subspace,
                 ec_tol=args.ec_tol, sq_order=args.sq_order, max_systems=args.max_systems,
-                flags=L.RPA_FLAG_PRECOND if args.precond else 0,
+                flags=L.RPA_FLAG_PRECOND if args.precond else 0, cocg_block=args.block,
                 freq_mode=L.RPA_WARM if args.freq_mode == "warm" else L.RPA_INDEPENDENT)
     if wl.subspace_iters > 0:
         opts.update(subspace_iters=wl.subspace_iters, ec_tol=0.0)
@@ -192,6 +195,13 @@ def main():
         achieved = alg / fwd / 1e9
         timing = "forward wall time (concurrent cells)"
     traffic, tb = cocg_traffic(wl.name, args.precision, pit / max(1, launches))
+    kernel = "cocg_wg (batched COCG, one workgroup per system)"
+    if args.precond or args.block >= 2:
+        # the host-driven solvers: a launch is a whole solve of several kernels, and the
+        # counters were taken on the plain kernel
+        kernel = ("host-driven %s (all kernels of a solve)" %
+                  ("block COCG" if args.block >= 2 else "preconditioned COCG"))
+        traffic, tb = None, None
     out = {
         "metric": "chi0 block-applies/s and time-to-E_c, FP32-refined batched vs FP64, 1 GPU",
         "value": applies / T,
@@ -206,7 +216,7 @@ def main():
                    "cocg_tol": wl.cocg_tol, "ec_tol": opts["ec_tol"],
                    "backward": not args.no_backward, "precision": args.precision,
                    "freq_mode": args.freq_mode, "sq_order": args.sq_order,
-                   "precond": bool(args.precond)},
+                   "precond": bool(args.precond), "cocg_block": args.block},
         "time_to_ec_s": float(np.mean([s["fwd_s"] for s in steps])),
         "backward_s": float(np.mean([s["bwd_s"] for s in steps])),
         "E_c": steps[-1]["E"],
@@ -214,7 +224,7 @@ def main():
         "chi0_applies_per_step": applies / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "cocg_wg (batched COCG, one workgroup per system)",
+                     "kernel": kernel,
                      "launches": launches, "avg_launch_ms": avg_ms,
                      "traffic_bytes_per_point_iter": tb,
                      "traffic_GBs": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
@@ -224,10 +234,10 @@ def main():
     if args.compare == "other":
         # the metric's comparison: the same path and inputs in the other precision (complex64
         # state with float64 reliable updates against complex128); a preconditioned run is
-        # compared with the plain FP64 solver instead
-        if args.precond:
+        # compared with the plain FP64 solver instead, and so is a block COCG run
+        if args.precond or args.block >= 2:
             other = "fp64"
-            o2 = dict(opts, flags=0)
+            o2 = dict(opts, flags=0, cocg_block=0)
         else:
             other = "mixed" if args.precision == "fp64" else "fp64"
             o2 = dict(opts, precision=L.RPA_MIXED if other == "mixed" else L.RPA_FP64)

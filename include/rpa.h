@@ -115,6 +115,18 @@ typedef struct rpa_options {
                                 tridiagonal).  The backward always differentiates the
                                 Rayleigh-Ritz energy of the saved subspaces, which the SQ
                                 energy converges to as the order grows. */
+    int32_t cocg_block;      /* 0 or 1 (default): every Sternheimer system is solved on its
+                                own.  2..8: block COCG (Sec. 3 names the block variant of
+                                the solver): the systems of one orbital n and one frequency
+                                share their matrix H - eps_n - i omega, so runs of up to
+                                cocg_block consecutive trial vectors with equal frequency
+                                (within one launch) are solved as one block with a shared
+                                Krylov space; a column leaves its block when its relative
+                                residual reaches cocg_tol.  With RPA_FLAG_PRECOND the block
+                                iteration is preconditioned by the Kronecker shifted
+                                Laplacian.  RPA_FP64 only (RPA_ENOTIMPL with RPA_MIXED);
+                                the state is that of RPA_FLAG_PRECOND (112 B per point and
+                                system). */
 } rpa_options;
 
 /* Counters accumulated by a call (added to the struct's current contents). */

@@ -18,11 +18,21 @@ Readings (the paper gives no formulas for the block variant): the columns still 
 form the live set L; a converged column is frozen (its x is final) and every k x k quantity
 of the next step is taken on L only (rho and beta on L x L, P and Z on the columns of L),
 so the block shrinks as its columns converge; columns with b = 0 are never live.  The small
-systems are solved by Gaussian elimination with partial pivoting, and a pivot of modulus
-<= 1e-14 times the largest modulus of the matrix is a breakdown of every live column.  The
-iteration count of a column is the number of products with A it took part in.  Groups are
-runs of trial vectors with equal frequency, cut into blocks of at most `width` consecutive
-vectors from the start of each run.
+systems are solved by Gaussian elimination with partial pivoting after scaling every row,
+then every column, to a largest modulus of one (the entries of rho and P^T Q scale with the
+residual norms of their columns, which differ by up to the tolerance ratio once some columns
+near convergence), and a pivot of modulus <= split_tol = 1e-3 of the scaled matrix means
+the block has lost rank: the residual columns of a block can become linearly dependent
+before they converge (on the 24^3 cell, three columns of a block of four reach rank one and
+stall long before their tolerance; splitting at 1e-14 instead of 1e-3 left the hardest
+blocks at 76-84 iterations instead of 26-28, and 1e-2 splits blocks that would converge).
+The block then splits: each of its live columns goes on as single-vector (P)COCG from its
+current x and r.  A failed alpha solve takes that step with the per-column alpha_c = rho_cc / (p_c^T q_c),
+and the next direction step restarts every column with p_c = z_c (beta = 0); a failed beta
+solve restarts at once.  A split column with a zero p_c^T q_c or r_c^T z_c breaks down.
+The iteration count of a column is the number of products with A it took part in.  Groups
+are runs of trial vectors with equal frequency, cut into blocks of at most `width`
+consecutive vectors from the start of each run.
 """
 import numpy as np
 
@@ -33,15 +43,25 @@ from .precond import kron_laplacian_inverse, precond_shift
 
 
 def gauss_solve(M, Rhs, breakdown_tol=1e-14):
-    """M^{-1} Rhs by Gaussian elimination with partial pivoting (row swaps by largest
-    modulus); None when a pivot's modulus is <= breakdown_tol * max |M_ij|."""
+    """M^{-1} Rhs: rows, then columns of M scaled to a largest modulus of one (D_r M D_c),
+    Gaussian elimination with partial pivoting (row swaps by largest modulus) on the scaled
+    system, x = D_c y; None when a row or column is zero or a pivot's modulus is
+    <= breakdown_tol."""
     A = np.array(M, dtype=np.complex128)
     Y = np.array(Rhs, dtype=np.complex128)
     n = A.shape[0]
-    scale = np.abs(A).max() if A.size else 0.0
+    rs = np.abs(A).max(axis=1) if n else np.zeros(0)
+    if np.any(~(rs > 0.0)):
+        return None
+    A /= rs[:, None]
+    Y /= rs[:, None]
+    cs = np.abs(A).max(axis=0)
+    if np.any(~(cs > 0.0)):
+        return None
+    A /= cs[None, :]
     for k in range(n):
         piv = k + int(np.argmax(np.abs(A[k:, k])))
-        if not abs(A[piv, k]) > breakdown_tol * scale:
+        if not abs(A[piv, k]) > breakdown_tol:
             return None
         if piv != k:
             A[[k, piv]] = A[[piv, k]]
@@ -52,13 +72,17 @@ def gauss_solve(M, Rhs, breakdown_tol=1e-14):
             Y[i] -= f * Y[k]
     for k in range(n - 1, -1, -1):
         Y[k] = (Y[k] - A[k, k + 1:] @ Y[k + 1:]) / A[k, k]
-    return Y
+    return Y / cs[:, None]
 
 
-def bcocg(apply_A, B, tol, max_iter, apply_M=None, breakdown_tol=1e-14):
+SPLIT_TOL = 1e-3
+
+
+def bcocg(apply_A, B, tol, max_iter, apply_M=None, split_tol=SPLIT_TOL):
     """Solve A X = B for the k columns of B by (preconditioned) block COCG.
 
     apply_A, apply_M: callables on (N, k') complex blocks; apply_M None is the identity.
+    split_tol: pivot threshold of the scaled small solves below which the block splits.
     Returns (X, iters, status) per column, status OK / NOT_CONVERGED / BREAKDOWN.
     """
     B = np.asarray(B, dtype=np.complex128)
@@ -77,6 +101,16 @@ def bcocg(apply_A, B, tol, max_iter, apply_M=None, breakdown_tol=1e-14):
     status = np.full(k, OK, dtype=np.int64)
     live = bnorm > 0.0
     rho = np.zeros((k, k), dtype=np.complex128)
+    split = 0          # 0: block; 1: split, restart pending; 2: split (single vectors)
+
+    def diag_solve(num, den, cols):
+        """num_cc / den_cc per column; a zero denominator breaks the column down."""
+        d = np.diag(den).copy()
+        bad = d == 0.0
+        status[cols[bad]] = BREAKDOWN
+        live[cols[bad]] = False
+        return np.diag(np.where(bad, 0.0, np.diag(num) / np.where(bad, 1.0, d)))
+
     L = np.nonzero(live)[0]
     if L.size:
         Z[:, L] = M(R[:, L])
@@ -85,15 +119,18 @@ def bcocg(apply_A, B, tol, max_iter, apply_M=None, breakdown_tol=1e-14):
     while L.size:
         Q = apply_A(P[:, L])
         G = P[:, L].T @ Q
-        alpha = gauss_solve(G, rho[np.ix_(L, L)], breakdown_tol)
         iters[L] += 1
-        if alpha is None:
-            status[L] = BREAKDOWN
-            break
+        alpha = None
+        if split == 0:
+            alpha = gauss_solve(G, rho[np.ix_(L, L)], split_tol)
+            if alpha is None:
+                split = 1
+        if split:
+            alpha = diag_solve(rho[np.ix_(L, L)], G, L)
         X[:, L] += P[:, L] @ alpha
         R[:, L] -= Q @ alpha
         conv = nrm(R[:, L]) <= tol * bnorm[L]
-        hit = (iters[L] >= max_iter) & ~conv
+        hit = (iters[L] >= max_iter) & ~conv & live[L]
         status[L[hit]] = NOT_CONVERGED
         live[L[conv | hit]] = False
         L = np.nonzero(live)[0]
@@ -101,12 +138,18 @@ def bcocg(apply_A, B, tol, max_iter, apply_M=None, breakdown_tol=1e-14):
             break
         Z[:, L] = M(R[:, L])
         rho_new = R[:, L].T @ Z[:, L]
-        beta = gauss_solve(rho[np.ix_(L, L)], rho_new, breakdown_tol)
-        if beta is None:
-            status[L] = BREAKDOWN
-            break
+        if split == 0:
+            beta = gauss_solve(rho[np.ix_(L, L)], rho_new, split_tol)
+            if beta is None:
+                split = 1
+        if split == 1:
+            beta = np.zeros((L.size, L.size), dtype=np.complex128)      # restart: p = z
+            split = 2
+        elif split == 2:
+            beta = diag_solve(rho_new, rho[np.ix_(L, L)], L)
         P[:, L] = Z[:, L] + P[:, L] @ beta
         rho[np.ix_(L, L)] = rho_new
+        L = np.nonzero(live)[0]
     return X, iters, status
 
 

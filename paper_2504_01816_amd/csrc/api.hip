@@ -58,6 +58,9 @@ struct Opts {
     double state_budget = 0.0;   // bytes of COCG state per launch when max_systems = 0 (set
                                  // below: the library default, or a cell's share of it)
     bool precond = false;        // RPA_FLAG_PRECOND
+    int block = 0;               // cocg_block: block COCG width (0, 1: off)
+    // the host-driven solver (split vectors): preconditioned or block COCG
+    bool host_driven() const { return precond || block >= 2; }
 };
 
 int fail(int code, const std::string& msg) {
@@ -79,6 +82,7 @@ int read_opts(const rpa_options* o, Opts* out) {
         d.sq_order = o->sq_order;
         if (o->flags & ~RPA_FLAG_PRECOND) return fail(RPA_EINVAL, "options.flags: unknown bits");
         d.precond = (o->flags & RPA_FLAG_PRECOND) != 0;
+        d.block = o->cocg_block;
     }
     if (d.precision != RPA_FP64 && d.precision != RPA_MIXED)
         return fail(RPA_EINVAL, "options.precision must be RPA_FP64 or RPA_MIXED");
@@ -96,6 +100,11 @@ int read_opts(const rpa_options* o, Opts* out) {
         return fail(RPA_EINVAL, "options.sq_order must be in [0, 32]");
     if (d.precond && d.precision != RPA_FP64)
         return fail(RPA_ENOTIMPL, "RPA_FLAG_PRECOND is implemented for RPA_FP64 only");
+    if (d.block < 0 || d.block > kMaxBlockWidth)
+        return fail(RPA_EINVAL, "options.cocg_block must be in [0, 8]");
+    if (d.block >= 2 && d.precision != RPA_FP64)
+        return fail(RPA_ENOTIMPL, "block COCG (options.cocg_block >= 2) is implemented for "
+                                  "RPA_FP64 only");
     *out = d;
     return RPA_OK;
 }
@@ -175,9 +184,14 @@ struct Chi0Buf {
     double* omega_v;  // per trial vector of a chunk: its frequency
     int* order;       // per system of a chunk: dispatch order
     double2* dbuf;  // backward only
-    // preconditioned solver (RPA_FLAG_PRECOND): split complex vectors, per-system scalars,
-    // the 1D eigenbases of the preconditioner and the mean of V_loc
-    bool precond;
+    // host-driven solver (RPA_FLAG_PRECOND or cocg_block >= 2): split complex vectors,
+    // per-system scalars, the 1D eigenbases of the preconditioner and the mean of V_loc;
+    // kron: apply K^{-1} (else the identity); block: block COCG width (0: single systems),
+    // boff: slot offsets of the blocks, bsplit: their split states, prho: rho per slot
+    // (block: 8 per slot)
+    bool precond, kron;
+    int block;
+    int *boff, *bsplit;
     double *pr, *pp, *pz, *pq, *ptmp;
     double2 *prho, *kshift;
     double* pb2;
@@ -194,6 +208,7 @@ struct Chi0Host {
     std::vector<int> hint;
     std::vector<double> om_chunk;
     std::vector<int> order, it, st, rf;
+    std::vector<int> boff;            // block COCG: slot offsets of the blocks
     double vmean = 0.0;               // mean V_loc (preconditioner shifts)
     std::vector<double2> kshift;      // per system of a chunk: (sigma_n, omega_j)
     void reset(int ns, int nvec, double w) {
@@ -208,9 +223,10 @@ struct Chi0Host {
 constexpr double kStateBudget = 128.0 * (1ull << 30);
 
 // COCG state per point and system: FP64 r, p_a, p_b complex128 + x; mixed 64 B; the
-// preconditioned solver keeps r, p, z, q, a transform buffer, x and b: 112 B.
+// host-driven solver (preconditioned or block COCG) keeps r, p, z, q, a transform buffer, x
+// and b: 112 B.
 double state_bytes_per_point(const Opts& o) {
-    return o.precond ? 112.0 : (o.precision == RPA_MIXED ? 64.0 : 56.0);
+    return o.host_driven() ? 112.0 : (o.precision == RPA_MIXED ? 64.0 : 56.0);
 }
 
 // Trial vectors per COCG launch: as many as the cap allows, split into chunks of equal size
@@ -241,7 +257,9 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     const int64_t nd = g.nd();
     b.nsplit = coeff_split(nd, ns, S);
     b.mixed = (o.precision == RPA_MIXED);
-    b.precond = o.precond;
+    b.precond = o.host_driven();
+    b.kron = o.precond;
+    b.block = o.block >= 2 ? o.block : 0;
     // the mixed path keeps its solution as complex float64 (x_hi) for the true residual; the
     // preconditioned solver keeps it complex as well
     b.x_complex = x_complex || b.mixed || b.precond;
@@ -271,10 +289,12 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
         b.pz = cv.take<double>(blk);
         b.pq = cv.take<double>(blk);
         b.ptmp = cv.take<double>(blk);
-        b.prho = cv.take<double2>(S);
+        b.prho = cv.take<double2>(size_t(S) * (b.block ? kMaxBlockWidth : 1));
         b.kshift = cv.take<double2>(S);
         b.pb2 = cv.take<double>(S);
         b.pactive = cv.take<int>(S);
+        b.boff = b.block ? cv.take<int>(S + 1) : nullptr;
+        b.bsplit = b.block ? cv.take<int>(S) : nullptr;
         b.Ux = cv.take<double>(size_t(g.n0) * g.n0);
         b.Uy = cv.take<double>(size_t(g.n1) * g.n1);
         b.Uz = cv.take<double>(size_t(g.n2) * g.n2);
@@ -289,6 +309,8 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
         b.prho = b.kshift = nullptr;
         b.pb2 = nullptr;
         b.pactive = nullptr;
+        b.boff = nullptr;
+        b.bsplit = nullptr;
         b.Ux = b.Uy = b.Uz = b.kx = b.ky = b.kz = b.bwork = b.vmean = nullptr;
     }
 }
@@ -507,6 +529,42 @@ void dispatch_order(const rpa_cell* cell, int nv, int64_t j0, Chi0Host& h) {
                      [&](int a, int b) { return key[a] > key[b]; });
 }
 
+// Block COCG: the systems n + ns j of one orbital n whose trial vectors j form a run of equal
+// frequency are cut into blocks of at most `width` consecutive vectors from the start of the
+// run; the blocks take consecutive slots, hardest first (the largest dispatch key of their
+// members, from h.order), and h.order becomes the slot -> system map, h.boff the offsets.
+void block_order(const rpa_cell* cell, int nv, int width, Chi0Host& h) {
+    const int ns = cell->n_occ, S = ns * nv;
+    std::vector<int> rank(S);
+    for (int t = 0; t < S; ++t) rank[h.order[t]] = t;   // position in the dispatch order
+    std::vector<std::vector<int>> blocks;
+    for (int j = 0; j < nv;) {
+        int e = j;
+        while (e < nv && h.om_chunk[e] == h.om_chunk[j]) ++e;
+        for (int a = j; a < e; a += width)
+            for (int n = 0; n < ns; ++n) {
+                std::vector<int> m;
+                for (int jj = a; jj < std::min(e, a + width); ++jj) m.push_back(n + ns * jj);
+                blocks.push_back(m);
+            }
+        j = e;
+    }
+    std::vector<int> first(blocks.size());
+    for (size_t k = 0; k < blocks.size(); ++k) {
+        first[k] = S;
+        for (int i : blocks[k]) first[k] = std::min(first[k], rank[i]);
+    }
+    std::vector<int> bo(blocks.size());
+    for (size_t k = 0; k < bo.size(); ++k) bo[k] = int(k);
+    std::stable_sort(bo.begin(), bo.end(), [&](int a, int c) { return first[a] < first[c]; });
+    h.order.clear();
+    h.boff.assign(1, 0);
+    for (int k : bo) {
+        for (int i : blocks[k]) h.order.push_back(i);
+        h.boff.push_back(int(h.order.size()));
+    }
+}
+
 // Solve the Sternheimer systems of the trial vectors j0 .. j0+nv-1 (columns of U, which
 // points at column j0), each at its own frequency h.omega[j].
 int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Buf& b,
@@ -527,10 +585,14 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
         // slots in dispatch order (longest solve first), so the systems still iterating stay
         // in a prefix of the slots that the preconditioner passes cover
         dispatch_order(cell, nv, j0, h);
+        if (b.block) block_order(cell, nv, b.block, h);
         RPA_HIP(hipMemcpyAsync(b.omega_v, h.om_chunk.data(), sizeof(double) * nv,
                                hipMemcpyHostToDevice, s));
         RPA_HIP(hipMemcpyAsync(b.order, h.order.data(), sizeof(int) * ns * nv,
                                hipMemcpyHostToDevice, s));
+        if (b.block)
+            RPA_HIP(hipMemcpyAsync(b.boff, h.boff.data(), sizeof(int) * h.boff.size(),
+                                   hipMemcpyHostToDevice, s));
         h.kshift.resize(size_t(ns) * nv);
         for (int t = 0; t < ns * nv; ++t) {
             const int i = h.order[t];
@@ -547,6 +609,11 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
         P.omega_v = b.omega_v;
         P.order = b.order;
         P.kshift = b.kshift;
+        P.width = b.block;
+        P.nblk = b.block ? int(h.boff.size()) - 1 : 0;
+        P.boff = b.boff;
+        P.split = b.bsplit;
+        P.kron = b.kron;
         P.tol = o.cocg_tol;
         P.max_iter = o.cocg_max_iter;
         P.rhs = reinterpret_cast<const double2*>(b.r);
@@ -1099,6 +1166,7 @@ int rpa_default_options(rpa_options* opt) {
     opt->max_systems = d.max_systems;
     opt->flags = 0;
     opt->sq_order = d.sq_order;
+    opt->cocg_block = 0;
     return RPA_OK;
 }
 

@@ -87,9 +87,18 @@ hipError_t launch_kron_precond(const Grid& g, int nsys, const double* in, double
 // host-driven iterations of batched kernels (one workgroup per system for the stencil,
 // reductions and updates; the preconditioner as Kronecker passes over all systems).  The
 // complex vectors r, p, z, q live as N_d x 2 nsys real column blocks.  See pcocg.hip.
+// Widest block of the block COCG solver.
+constexpr int kMaxBlockWidth = 8;
+
 struct PcocgLaunch {
     Grid g;
     int nsys, ns;
+    // block COCG: width >= 2 (at most kMaxBlockWidth); the slots of block b are
+    // boff[b] .. boff[b+1]-1 (device, nblk + 1 offsets); 0: every system on its own
+    int width = 0, nblk = 0;
+    const int* boff = nullptr;
+    int* split = nullptr;   // device, nsys: per-block split state (at the block's first slot)
+    bool kron = true;       // apply K^{-1} (false: the identity, block COCG only)
     const double* vloc;
     const double* eps;      // device, ns
     const double* omega_v;  // device, nsys / ns: frequency of trial vector j
@@ -100,7 +109,7 @@ struct PcocgLaunch {
     const double2* rhs;     // nsys x N_d complex (interleaved): right-hand sides
     double2* x;             // nsys x N_d complex (interleaved): solutions
     double *r, *p, *z, *q, *tmp;   // N_d x 2 nsys each
-    double2* rho;           // nsys
+    double2* rho;           // nsys (block COCG: nsys x kMaxBlockWidth)
     double* b2;             // nsys
     int *active, *iters, *status;  // nsys
     const double *Ux, *Uy, *Uz, *kx, *ky, *kz;

@@ -57,6 +57,10 @@ struct PcArgs {
     double* b2;
     int *active, *iters, *status;
     const int* order;   // slot t holds system order[t]
+    int qonly;          // the step stores q = A p and stops (block COCG)
+    const int* boff;    // block COCG: slots of block b are boff[b] .. boff[b+1]-1
+    int* split;         // block COCG, per slot (block b at boff[b]): 0 block, 1 split with a
+                        // restart pending, 2 split (single-vector iterations)
 };
 
 // Sum of NV values over the workgroup, in a fixed order (wave butterfly, then waves in order);
@@ -101,6 +105,7 @@ __global__ __launch_bounds__(PB) void pc_start(PcArgs a) {
         a.active[s] = acc[0] > 0.0 ? 1 : 0;
         a.iters[sys] = 0;
         a.status[sys] = 0;
+        if (a.split) a.split[s] = 0;
     }
 }
 
@@ -158,6 +163,7 @@ __global__ __launch_bounds__(PB) void pc_step(PcArgs a, int it) {
         acc[2] += p0r * p0r + p0i * p0i;
         acc[3] += vr * vr + vi * vi;
     }
+    if (a.qonly) return;
     pc_reduce<4>(acc, red);
     const double s2 = acc[0] * acc[0] + acc[1] * acc[1];
     if (!(s2 > a.bd_tol * a.bd_tol * acc[2] * acc[3])) {   // vanishing p^T q: breakdown
@@ -241,6 +247,406 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
         pi[i] = zi[i] + br * o1 + bi * o0;
     }
     if (threadIdx.x == 0) a.rho[s] = double2{acc[0], acc[1]};
+}
+
+// ------------------------------------------------------------------ block COCG
+// Block COCG over the systems of one orbital and one frequency (one matrix A, one K^{-1}),
+// one workgroup per block of w <= kMaxBlockWidth consecutive slots.  The columns still
+// iterating form the live set L (active flags); a converged column is frozen and every
+// w x w quantity is taken on L:
+//     q = A p on the live slots                                   (step kernel, q only)
+//     alpha = (P^T Q)^{-1} rho; X += P alpha; R -= Q alpha; tests   (bc_update)
+//     Z = M R on the live slots                                   (preconditioner passes)
+//     rho' = R^T Z; beta = rho^{-1} rho'; P = Z + P beta; rho = rho' (bc_dir)
+// The w x w matrices are reduced in a fixed order and solved by one thread; rho is kept per
+// block as rows of kMaxBlockWidth entries, row c at slot s0 + c.  A block whose residual
+// columns lose rank (a small solve with a scaled pivot <= kSplitTol) splits: its live columns
+// go on as single-vector iterations (diagonal alpha and beta), restarting with p = z at the
+// next direction step.
+constexpr int LDW = kMaxBlockWidth;
+// Pivot threshold of the scaled small solves below which a block counts as rank deficient and
+// splits (at 1e-14 the hardest 24^3 blocks stall for 50 steps before the test trips; 1e-2
+// splits blocks that would converge).
+constexpr double kSplitTol = 1e-3;
+constexpr int BPB = 256;    // threads per block-COCG workgroup (one block per workgroup)
+
+__device__ __forceinline__ double2 cmul(double2 u, double2 v) {
+    return double2{u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x};
+}
+__device__ __forceinline__ double2 cdiv(double2 u, double2 v) {
+    const double d = v.x * v.x + v.y * v.y;
+    return double2{(u.x * v.x + u.y * v.y) / d, (u.y * v.x - u.x * v.y) / d};
+}
+__device__ __forceinline__ double cmod(double2 u) { return hypot(u.x, u.y); }
+
+// Y <- M^{-1} Y for the n x n leading parts of row-major LDW x LDW arrays (M is destroyed):
+// rows, then columns of M scaled to a largest modulus of one (the entries scale with the
+// residual norms of their columns, which differ by up to the tolerance ratio), Gaussian
+// elimination with partial pivoting (first row of largest modulus), back substitution and the
+// column scales.  false when a row or column is zero or a pivot's modulus is <= bd_tol.
+// cs: LDW doubles of LDS for the column scales.
+__device__ bool small_solve(double2* M, double2* Y, int n, double bd_tol, double* cs) {
+    for (int i = 0; i < n; ++i) {
+        double m = 0.0;
+        for (int j = 0; j < n; ++j) m = fmax(m, cmod(M[i * LDW + j]));
+        if (!(m > 0.0)) return false;
+        for (int j = 0; j < n; ++j) {
+            M[i * LDW + j].x /= m;
+            M[i * LDW + j].y /= m;
+            Y[i * LDW + j].x /= m;
+            Y[i * LDW + j].y /= m;
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = fmax(m, cmod(M[i * LDW + j]));
+        if (!(m > 0.0)) return false;
+        for (int i = 0; i < n; ++i) {
+            M[i * LDW + j].x /= m;
+            M[i * LDW + j].y /= m;
+        }
+        cs[j] = m;
+    }
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = cmod(M[k * LDW + k]);
+        for (int i = k + 1; i < n; ++i) {
+            const double m = cmod(M[i * LDW + k]);
+            if (m > best) {
+                best = m;
+                piv = i;
+            }
+        }
+        if (!(best > bd_tol)) return false;
+        if (piv != k)
+            for (int j = 0; j < n; ++j) {
+                const double2 t = M[k * LDW + j];
+                M[k * LDW + j] = M[piv * LDW + j];
+                M[piv * LDW + j] = t;
+                const double2 u = Y[k * LDW + j];
+                Y[k * LDW + j] = Y[piv * LDW + j];
+                Y[piv * LDW + j] = u;
+            }
+        for (int i = k + 1; i < n; ++i) {
+            const double2 f = cdiv(M[i * LDW + k], M[k * LDW + k]);
+            for (int j = k; j < n; ++j) {
+                const double2 t = cmul(f, M[k * LDW + j]);
+                M[i * LDW + j].x -= t.x;
+                M[i * LDW + j].y -= t.y;
+            }
+            for (int j = 0; j < n; ++j) {
+                const double2 t = cmul(f, Y[k * LDW + j]);
+                Y[i * LDW + j].x -= t.x;
+                Y[i * LDW + j].y -= t.y;
+            }
+        }
+    }
+    for (int k = n - 1; k >= 0; --k)
+        for (int j = 0; j < n; ++j) {
+            double2 acc = Y[k * LDW + j];
+            for (int l = k + 1; l < n; ++l) {
+                const double2 t = cmul(M[k * LDW + l], Y[l * LDW + j]);
+                acc.x -= t.x;
+                acc.y -= t.y;
+            }
+            Y[k * LDW + j] = cdiv(acc, M[k * LDW + k]);
+        }
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j) {
+            Y[k * LDW + j].x /= cs[k];
+            Y[k * LDW + j].y /= cs[k];
+        }
+    return true;
+}
+
+// Live mask of the block at slots s0 .. s0+w-1 (bit c: slot s0 + c still iterating).
+__device__ __forceinline__ unsigned block_live(const PcArgs& a, int s0, int w) {
+    unsigned m = 0;
+    for (int c = 0; c < w; ++c)
+        if (a.active[s0 + c]) m |= 1u << c;
+    return m;
+}
+
+// Rows of the block Gram matrices reduced per pass (bounds the accumulator registers).
+template <int SM>
+constexpr int gram_rows() { return SM < 4 ? SM : 4; }
+
+// out[k] = sum over the workgroup of v[k] (LDS), in a fixed order: a butterfly in every wave,
+// one value at a time (a scheduling barrier keeps one value's shuffles in flight), then the
+// waves in order.  Ends with a barrier.
+template <int NV>
+__device__ void gram_reduce(const double (&v)[NV], double* red, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) red[wave * NV + k] = x;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[w * NV + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// gm[2 (c SM + d) + {0, 1}] = u_c^T v_d (unconjugated) over the live pairs (LDS), reduced over
+// the workgroup in a fixed order, rows in passes of gram_rows.
+template <int SM>
+__device__ void block_gram(const double* u, const double* v, int s0, unsigned live, int64_t nd,
+                           double* gm, double* red) {
+    constexpr int RB = gram_rows<SM>();
+#pragma unroll 1
+    for (int c0 = 0; c0 < SM; c0 += RB) {
+        if (!(live >> c0 & ((1u << RB) - 1u))) continue;
+        double acc[2 * RB * SM];
+        for (int k = 0; k < 2 * RB * SM; ++k) acc[k] = 0.0;
+#pragma unroll 1
+        for (int64_t i = threadIdx.x; i < nd; i += BPB) {
+            double2 vv[SM];
+#pragma unroll
+            for (int d = 0; d < SM; ++d)
+                if (live >> d & 1u) {
+                    const double* vd = v + nd * (2 * int64_t(s0 + d));
+                    vv[d] = double2{vd[i], vd[i + nd]};
+                }
+#pragma unroll
+            for (int cc = 0; cc < RB; ++cc) {
+                if (!(live >> (c0 + cc) & 1u)) continue;
+                const double* uc = u + nd * (2 * int64_t(s0 + c0 + cc));
+                const double2 uu{uc[i], uc[i + nd]};
+#pragma unroll
+                for (int d = 0; d < SM; ++d)
+                    if (live >> d & 1u) {
+                        acc[2 * (cc * SM + d)] += uu.x * vv[d].x - uu.y * vv[d].y;
+                        acc[2 * (cc * SM + d) + 1] += uu.x * vv[d].y + uu.y * vv[d].x;
+                    }
+            }
+        }
+        gram_reduce<2 * RB * SM>(acc, red, gm + 2 * c0 * SM);
+    }
+}
+
+// Compacts the live rows and columns of an SM x SM matrix held as (re, im) pairs into the
+// leading nl x nl part of dst.
+template <int SM>
+__device__ int compact_acc(const double* acc, unsigned live, double2* dst) {
+    int r = 0;
+    for (int c = 0; c < SM; ++c) {
+        if (!(live >> c & 1u)) continue;
+        int q = 0;
+        for (int d = 0; d < SM; ++d) {
+            if (!(live >> d & 1u)) continue;
+            dst[r * LDW + q] = double2{acc[2 * (c * SM + d)], acc[2 * (c * SM + d) + 1]};
+            ++q;
+        }
+        ++r;
+    }
+    return r;
+}
+
+// Scatters the leading nl x nl part of src (live order) to the full w x w layout of dst
+// (zero outside the live rows and columns).
+__device__ void expand_live(const double2* src, unsigned live, int w, double2* dst) {
+    int r = 0;
+    for (int c = 0; c < LDW; ++c) {
+        const bool lc = c < w && (live >> c & 1u);
+        int q = 0;
+        for (int d = 0; d < LDW; ++d) {
+            const bool ld = d < w && (live >> d & 1u);
+            dst[c * LDW + d] = (lc && ld) ? src[r * LDW + q] : double2{0.0, 0.0};
+            q += ld ? 1 : 0;
+        }
+        r += lc ? 1 : 0;
+    }
+}
+
+// G = P^T Q on L; alpha = G^{-1} rho; X += P alpha; R -= Q alpha; convergence and cap tests.
+template <int SM>
+__global__ __launch_bounds__(BPB) void bc_update(PcArgs a, int it) {
+    __shared__ double red[(BPB / 64) * 2 * gram_rows<SM>() * SM];
+    __shared__ double acc[2 * SM * SM];
+    __shared__ double2 G[LDW * LDW], Y[LDW * LDW], AL[LDW * LDW];
+    __shared__ double cs[LDW];
+    const int s0 = a.boff[blockIdx.x], w = a.boff[blockIdx.x + 1] - s0;
+    const unsigned live = block_live(a, s0, w);
+    if (!live) return;
+    const int64_t nd = a.nd;
+    const int sp = a.split[s0];
+    block_gram<SM>(a.p, a.q, s0, live, nd, acc, red);
+    if (threadIdx.x == 0) {
+        bool ok = false;
+        if (sp == 0) {
+            const int nl = compact_acc<SM>(acc, live, G);
+            int r = 0;
+            for (int c = 0; c < w; ++c) {
+                if (!(live >> c & 1u)) continue;
+                int q = 0;
+                for (int d = 0; d < w; ++d)
+                    if (live >> d & 1u) Y[r * LDW + q++] = a.rho[(s0 + c) * LDW + d];
+                ++r;
+            }
+            ok = small_solve(G, Y, nl, kSplitTol, cs);
+            if (ok) expand_live(Y, live, w, AL);
+            else a.split[s0] = 1;
+        }
+        if (!ok) {
+            // split: alpha_c = rho_cc / (p_c^T q_c); a zero denominator breaks the column down
+            for (int e = 0; e < LDW * LDW; ++e) AL[e] = double2{0.0, 0.0};
+            for (int c = 0; c < SM; ++c) {
+                if (!(live >> c & 1u)) continue;
+                const double2 g{acc[2 * (c * SM + c)], acc[2 * (c * SM + c) + 1]};
+                if (g.x == 0.0 && g.y == 0.0) {
+                    a.status[a.order[s0 + c]] = 2;
+                    a.active[s0 + c] = 0;
+                } else {
+                    AL[c * LDW + c] = cdiv(a.rho[(s0 + c) * LDW + c], g);
+                }
+            }
+        }
+        for (int c = 0; c < w; ++c)
+            if (live >> c & 1u) a.iters[a.order[s0 + c]] = it;
+    }
+    __syncthreads();
+    double nrm[SM];
+    for (int c = 0; c < SM; ++c) nrm[c] = 0.0;
+    for (int64_t i = threadIdx.x; i < nd; i += BPB) {
+        double2 pv[SM], qv[SM];
+#pragma unroll
+        for (int k = 0; k < SM; ++k)
+            if (live >> k & 1u) {
+                const double* pk = a.p + nd * (2 * int64_t(s0 + k));
+                const double* qk = a.q + nd * (2 * int64_t(s0 + k));
+                pv[k] = double2{pk[i], pk[i + nd]};
+                qv[k] = double2{qk[i], qk[i + nd]};
+            }
+#pragma unroll
+        for (int c = 0; c < SM; ++c) {
+            if (!(live >> c & 1u)) continue;
+            double2 dx{0.0, 0.0}, dr{0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < SM; ++k)
+                if (live >> k & 1u) {
+                    const double2 al = AL[k * LDW + c];
+                    const double2 t = cmul(pv[k], al), u = cmul(qv[k], al);
+                    dx.x += t.x;
+                    dx.y += t.y;
+                    dr.x += u.x;
+                    dr.y += u.y;
+                }
+            double2* xc = a.x + int64_t(a.order[s0 + c]) * nd;
+            double2 xv = xc[i];
+            xv.x += dx.x;
+            xv.y += dx.y;
+            xc[i] = xv;
+            double* rc = a.r + nd * (2 * int64_t(s0 + c));
+            const double nr = rc[i] - dr.x, ni = rc[i + nd] - dr.y;
+            rc[i] = nr;
+            rc[i + nd] = ni;
+            nrm[c] += nr * nr + ni * ni;
+        }
+    }
+    pc_reduce<SM>(nrm, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < w; ++c) {
+            if (!(live >> c & 1u) || !a.active[s0 + c]) continue;   // broken down above
+            if (nrm[c] <= a.tol2 * a.b2[s0 + c]) {
+                a.active[s0 + c] = 0;
+            } else if (it >= a.max_iter) {
+                a.status[a.order[s0 + c]] = 1;
+                a.active[s0 + c] = 0;
+            }
+        }
+}
+
+// rho' = R^T Z on L; first: P = Z; else beta = rho^{-1} rho', P = Z + P beta; rho = rho'.
+// A split block restarts (beta = 0) once, then takes beta_c = rho'_cc / rho_cc.
+template <int SM>
+__global__ __launch_bounds__(BPB) void bc_dir(PcArgs a, int first) {
+    __shared__ double red[(BPB / 64) * 2 * gram_rows<SM>() * SM];
+    __shared__ double acc[2 * SM * SM];
+    __shared__ double2 G[LDW * LDW], Y[LDW * LDW], BE[LDW * LDW];
+    __shared__ double cs[LDW];
+    const int s0 = a.boff[blockIdx.x], w = a.boff[blockIdx.x + 1] - s0;
+    const unsigned live = block_live(a, s0, w);
+    if (!live) return;
+    const int64_t nd = a.nd;
+    const int sp = a.split[s0];
+    block_gram<SM>(a.r, a.z, s0, live, nd, acc, red);
+    if (threadIdx.x == 0 && !first) {
+        bool ok = false;
+        if (sp == 0) {
+            const int nl = compact_acc<SM>(acc, live, Y);
+            int r = 0;
+            for (int c = 0; c < w; ++c) {
+                if (!(live >> c & 1u)) continue;
+                int q = 0;
+                for (int d = 0; d < w; ++d)
+                    if (live >> d & 1u) G[r * LDW + q++] = a.rho[(s0 + c) * LDW + d];
+                ++r;
+            }
+            ok = small_solve(G, Y, nl, kSplitTol, cs);
+            if (ok) expand_live(Y, live, w, BE);
+        }
+        if (!ok) {
+            for (int e = 0; e < LDW * LDW; ++e) BE[e] = double2{0.0, 0.0};
+            if (sp == 2) {
+                // split: beta_c = rho'_cc / rho_cc; a zero rho_cc breaks the column down
+                for (int c = 0; c < SM; ++c) {
+                    if (!(live >> c & 1u)) continue;
+                    const double2 d = a.rho[(s0 + c) * LDW + c];
+                    if (d.x == 0.0 && d.y == 0.0) {
+                        a.status[a.order[s0 + c]] = 2;
+                        a.active[s0 + c] = 0;
+                    } else {
+                        BE[c * LDW + c] = cdiv(double2{acc[2 * (c * SM + c)],
+                                                       acc[2 * (c * SM + c) + 1]}, d);
+                    }
+                }
+            } else {
+                a.split[s0] = 2;   // restart: p = z
+            }
+        }
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < SM; ++c)
+            for (int d = 0; d < SM; ++d)
+                if ((live >> c & 1u) && (live >> d & 1u))
+                    a.rho[(s0 + c) * LDW + d] =
+                        double2{acc[2 * (c * SM + d)], acc[2 * (c * SM + d) + 1]};
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < nd; i += BPB) {
+        double2 pv[SM];
+        if (!first) {
+#pragma unroll
+            for (int k = 0; k < SM; ++k)
+                if (live >> k & 1u) {
+                    const double* pk = a.p + nd * (2 * int64_t(s0 + k));
+                    pv[k] = double2{pk[i], pk[i + nd]};
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < SM; ++c) {
+            if (!(live >> c & 1u)) continue;
+            const double* zc = a.z + nd * (2 * int64_t(s0 + c));
+            double2 v{zc[i], zc[i + nd]};
+            if (!first) {
+#pragma unroll
+                for (int k = 0; k < SM; ++k)
+                    if (live >> k & 1u) {
+                        const double2 t = cmul(pv[k], BE[k * LDW + c]);
+                        v.x += t.x;
+                        v.y += t.y;
+                    }
+            }
+            double* pc = a.p + nd * (2 * int64_t(s0 + c));
+            pc[i] = v.x;
+            pc[i + nd] = v.y;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ fused preconditioner
@@ -445,6 +851,7 @@ void pc_step_wg(PcArgs pa, cocg::Args ca, int it) {
         }
         cocg::march<double, double2, 1, 1, SLAB>(a, cl, planes, eps_n, lead, cent, Q, false);
     }
+    if (pa.qonly) return;
     cocg::wg_reduce<4>(cent.acc, red);
     const double s2 = cent.acc[0] * cent.acc[0] + cent.acc[1] * cent.acc[1];
     if (!(s2 > pa.bd_tol * pa.bd_tol * cent.acc[2] * cent.acc[3])) {   // breakdown
@@ -591,6 +998,55 @@ hipError_t apply_precond(const PcocgLaunch& L, int nsys, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Block COCG: the step kernel stores q = A p for the live slots, the block kernels do the
+// rest; z aliases r without the preconditioner.  a is the step kernel's argument block.
+template <typename Step>
+hipError_t run_block(const PcocgLaunch& L, PcArgs& a, dim3 grid, Step& step, int& prefix,
+                     hipStream_t s) {
+    a.qonly = 1;
+    a.boff = L.boff;
+    a.split = L.split;
+    if (!L.kron) a.z = a.r;
+    const dim3 bgrid(unsigned(L.nblk)), block(BPB);
+    const int sm = L.width <= 2 ? 2 : (L.width <= 4 ? 4 : 8);
+    auto update = [&](int it) {
+        if (sm == 2) hipLaunchKernelGGL(bc_update<2>, bgrid, block, 0, s, a, it);
+        else if (sm == 4) hipLaunchKernelGGL(bc_update<4>, bgrid, block, 0, s, a, it);
+        else hipLaunchKernelGGL(bc_update<8>, bgrid, block, 0, s, a, it);
+        return hipGetLastError();
+    };
+    auto dir = [&](int first) {
+        if (sm == 2) hipLaunchKernelGGL(bc_dir<2>, bgrid, block, 0, s, a, first);
+        else if (sm == 4) hipLaunchKernelGGL(bc_dir<4>, bgrid, block, 0, s, a, first);
+        else hipLaunchKernelGGL(bc_dir<8>, bgrid, block, 0, s, a, first);
+        return hipGetLastError();
+    };
+    hipLaunchKernelGGL(pc_start, grid, block, 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (L.kron && (e = apply_precond(L, prefix, s)) != hipSuccess) return e;
+    if ((e = dir(1)) != hipSuccess) return e;
+    std::vector<int> act(L.nsys);
+    for (int it = 1; it <= L.max_iter; ++it) {
+        if ((e = step(it)) != hipSuccess) return e;
+        if ((e = update(it)) != hipSuccess) return e;
+        if (it % kCheckEvery == 0 || it == L.max_iter) {
+            if ((e = hipMemcpyAsync(act.data(), L.active, sizeof(int) * L.nsys,
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+            prefix = 0;
+            for (int t = 0; t < L.nsys; ++t)
+                if (act[t]) prefix = t + 1;
+            if (prefix == 0) break;
+        }
+        if (it == L.max_iter) break;
+        if (L.kron && (e = apply_precond(L, prefix, s)) != hipSuccess) return e;
+        if ((e = dir(0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
     if (L.nsys <= 0) return hipSuccess;
     PcArgs a{};
@@ -655,6 +1111,7 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
         return hipGetLastError();
     };
     auto precond = [&]() { return apply_precond(L, prefix, s); };
+    if (L.width >= 2) return run_block(L, a, grid, step, prefix, s);
     hipLaunchKernelGGL(pc_start, grid, block, 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -65,7 +65,8 @@ def cmd_apply(args):
     nvec = args.nvec or wl.n_r[0]
     X = api.rpa_apply_coulomb(dc, torch.tensor(wl.V0[0][:nvec], device="cuda:0"), 1)
     prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
-    opts = dict(precision=prec, cocg_tol=wl.cocg_tol, flags=L.RPA_FLAG_PRECOND if args.precond else 0)
+    opts = dict(precision=prec, cocg_tol=wl.cocg_tol, flags=L.RPA_FLAG_PRECOND if args.precond else 0,
+                cocg_block=args.block)
     tot = {"cocg_point_iters": 0.0, "cocg_launches": 0, "cocg_kernel_ms": 0.0, "cocg_iters_total": 0}
     idx = range(len(wl.omegas)) if args.omega_index < 0 else [args.omega_index]
     if args.warmup:
@@ -81,7 +82,7 @@ def cmd_apply(args):
             tot[k] += st[k]
     torch.cuda.synchronize()
     tot.update(workload=wl.name, precision=args.precision, nvec=nvec, omegas=list(idx),
-               precond=bool(args.precond))
+               precond=bool(args.precond), block=args.block)
     print(json.dumps(tot), file=sys.stderr)
     if args.out:
         with open(args.out, "w") as f:
@@ -270,6 +271,8 @@ def main():
     a.add_argument("--warmup", action="store_true", help="one untimed apply first")
     a.add_argument("--precond", action="store_true",
                    help="preconditioned COCG (Kronecker shifted-Laplacian preconditioner)")
+    a.add_argument("--block", type=int, default=0,
+                   help="block COCG width (options.cocg_block; 0: single systems)")
     ss = sub.add_parser("subspace")
     ss.add_argument("--gen-device", action="store_true")
     ss.add_argument("--config", type=int, default=2)

@@ -178,6 +178,29 @@ def test_option_flags_are_validated_on_the_host(so):
     assert pre.value > plain.value + 16 * 4 * 12 ** 3 * 80
 
 
+def test_block_width_is_validated_on_the_host(so):
+    c = _cell()
+    for bad in (-1, 9):
+        o = L.default_options(cocg_block=bad)
+        assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(o), None,
+                                 0x5000, 1 << 30, None) == L.RPA_EINVAL
+        assert "cocg_block" in L.last_error()
+    o = L.default_options(cocg_block=4, precision=L.RPA_MIXED)
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, ctypes.byref(o), None,
+                             0x5000, 1 << 30, None) == L.RPA_ENOTIMPL
+    assert L.default_options().cocg_block == 0
+    # block COCG keeps the split state of the preconditioned solver plus the block matrices
+    nv = (ctypes.c_int32 * 1)(16)
+    pre, blk = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    o = L.default_options(flags=L.RPA_FLAG_PRECOND)
+    assert so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(c), nv, 1, ctypes.byref(o),
+                                 ctypes.byref(pre)) == 0
+    o = L.default_options(cocg_block=4)
+    assert so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(c), nv, 1, ctypes.byref(o),
+                                 ctypes.byref(blk)) == 0
+    assert blk.value >= pre.value + 4 * 16 * 7 * 16
+
+
 def test_chi0_rejects_bad_scalars_and_workspace(so):
     c = _cell(eps=[0.0, 1.0, 0.5, 2.0])                     # not ascending
     assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5000, 1 << 30,

@@ -27,20 +27,27 @@ def test_gauss_solve_equals_library_solve_and_flags_singular():
     Ms[:, 4] = 2.0 * Ms[:, 1]                       # rank deficient
     assert gauss_solve(Ms, Y) is None
     assert gauss_solve(np.zeros((2, 2)), np.ones((2, 2))) is None
+    # the breakdown test does not depend on the scale of rows and columns: residual blocks
+    # whose columns differ in norm by 1e-10 give rho entries 1e-20 apart
+    D = np.diag([1.0, 1e-10, 1.0, 1e-12, 1.0, 1e-9])
+    X = gauss_solve(D @ M @ D, D @ Y)
+    assert X is not None
+    np.testing.assert_allclose(X, np.linalg.solve(D @ M @ D, D @ Y), rtol=1e-10)
 
 
 def test_block_terminates_within_n_over_k_steps():
-    # in exact arithmetic block COCG on k columns spans the whole space after N/k steps
+    # in exact arithmetic block COCG on k columns spans the whole space after N/k steps (the
+    # pure block recurrence: no split, whose threshold would trip on the last, exhausted step)
     rng = np.random.default_rng(2)
     N, k = 24, 4
     A = _sym(rng, N, 3.0 + 0.5j)
     B = rng.standard_normal((N, k)) + 1j * rng.standard_normal((N, k))
-    X, it, st = bcocg(lambda P: A @ P, B, 1e-11, 50)
+    X, it, st = bcocg(lambda P: A @ P, B, 1e-11, 50, split_tol=1e-14)
     assert np.all(st == OK) and it.max() <= N // k
     np.testing.assert_allclose(X, np.linalg.solve(A, B), rtol=1e-10, atol=1e-12)
     # preconditioned by a complex symmetric M (inverse Jacobi): the same bound
     Mi = np.diag(1.0 / np.diag(A))
-    X, it, st = bcocg(lambda P: A @ P, B, 1e-11, 50, lambda R: Mi @ R)
+    X, it, st = bcocg(lambda P: A @ P, B, 1e-11, 50, lambda R: Mi @ R, split_tol=1e-14)
     assert np.all(st == OK) and it.max() <= N // k
     np.testing.assert_allclose(X, np.linalg.solve(A, B), rtol=1e-10, atol=1e-12)
 
@@ -73,6 +80,23 @@ def test_zero_column_never_enters_the_block():
     assert it0[1] == 0 and st0[1] == OK and np.all(X0[:, 1] == 0.0)
     assert np.array_equal(np.delete(it0, 1), it)
     assert np.array_equal(np.delete(X0, 1, axis=1), X)
+
+
+def test_rank_deficient_block_splits_into_single_vector_solves():
+    # two equal right-hand sides: P^T A P is singular at the first step, the block splits and
+    # every column is solved (the equal pair identically) as by single-vector COCG
+    rng = np.random.default_rng(6)
+    A = _sym(rng, 40, 1.5 + 0.2j)
+    B = rng.standard_normal((40, 3)) + 1j * rng.standard_normal((40, 3))
+    B[:, 2] = B[:, 0]
+    X, it, st = bcocg(lambda P: A @ P, B, 1e-11, 200)
+    assert np.all(st == OK)
+    np.testing.assert_allclose(X, np.linalg.solve(A, B), rtol=1e-9, atol=1e-12)
+    assert np.array_equal(X[:, 0], X[:, 2]) and it[0] == it[2]
+    # after the split (one step along the block directions, then restarts) each column
+    # follows single-vector COCG from its own iterate
+    _, it1, _ = pcocg_batched(lambda V: A @ V, np.zeros(3), B, 1e-11, 200)
+    assert np.all(np.abs(it - it1) <= 2)
 
 
 def test_iteration_cap_reports_not_converged():
