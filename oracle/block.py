@@ -17,7 +17,11 @@ X_0 = 0 and M the preconditioner (the identity for unpreconditioned block COCG):
 Readings (the paper gives no formulas for the block variant): the columns still iterating
 form the live set L; a converged column is frozen (its x is final) and every k x k quantity
 of the next step is taken on L only (rho and beta on L x L, P and Z on the columns of L),
-so the block shrinks as its columns converge; columns with b = 0 are never live.  The small
+so the block shrinks as its columns converge; columns with b = 0 are never live.  When L
+shrinks, the block restarts on its remaining columns (beta = 0, P_L = Z_L): the directions
+kept from the larger block are no longer conjugate within the smaller one, and on the 24^3
+cell keeping them leaves single columns at 76-124 steps where their blocks converged in
+20-24 (with the restart: 23-24).  The small
 systems are solved by Gaussian elimination with partial pivoting after scaling every row,
 then every column, to a largest modulus of one (the entries of rho and P^T Q scale with the
 residual norms of their columns, which differ by up to the tolerance ratio once some columns
@@ -133,12 +137,15 @@ def bcocg(apply_A, B, tol, max_iter, apply_M=None, split_tol=SPLIT_TOL):
         hit = (iters[L] >= max_iter) & ~conv & live[L]
         status[L[hit]] = NOT_CONVERGED
         live[L[conv | hit]] = False
+        shrank = L.size > int(np.count_nonzero(live))
         L = np.nonzero(live)[0]
         if not L.size:
             break
         Z[:, L] = M(R[:, L])
         rho_new = R[:, L].T @ Z[:, L]
-        if split == 0:
+        if split == 0 and shrank:
+            beta = np.zeros((L.size, L.size), dtype=np.complex128)      # deflated: restart
+        elif split == 0:
             beta = gauss_solve(rho[np.ix_(L, L)], rho_new, split_tol)
             if beta is None:
                 split = 1

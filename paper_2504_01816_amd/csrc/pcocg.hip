@@ -59,8 +59,9 @@ struct PcArgs {
     const int* order;   // slot t holds system order[t]
     int qonly;          // the step stores q = A p and stops (block COCG)
     const int* boff;    // block COCG: slots of block b are boff[b] .. boff[b+1]-1
-    int* split;         // block COCG, per slot (block b at boff[b]): 0 block, 1 split with a
-                        // restart pending, 2 split (single-vector iterations)
+    int* split;         // block COCG, per slot (block b at boff[b]): state + 4 * live mask at
+                        // the last direction step; state 0 block, 1 split with a restart
+                        // pending, 2 split (single-vector iterations)
 };
 
 // Sum of NV values over the workgroup, in a fixed order (wave butterfly, then waves in order);
@@ -259,10 +260,11 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
 //     Z = M R on the live slots                                   (preconditioner passes)
 //     rho' = R^T Z; beta = rho^{-1} rho'; P = Z + P beta; rho = rho' (bc_dir)
 // The w x w matrices are reduced in a fixed order and solved by one thread; rho is kept per
-// block as rows of kMaxBlockWidth entries, row c at slot s0 + c.  A block whose residual
-// columns lose rank (a small solve with a scaled pivot <= kSplitTol) splits: its live columns
-// go on as single-vector iterations (diagonal alpha and beta), restarting with p = z at the
-// next direction step.
+// block as rows of kMaxBlockWidth entries, row c at slot s0 + c.  When columns converge the
+// block restarts on the rest (beta = 0: the kept directions are not conjugate within the
+// smaller block).  A block whose residual columns lose rank (a small solve with a scaled pivot
+// <= kSplitTol) splits: its live columns go on as single-vector iterations (diagonal alpha
+// and beta), restarting with p = z at the next direction step.
 constexpr int LDW = kMaxBlockWidth;
 // Pivot threshold of the scaled small solves below which a block counts as rank deficient and
 // splits (at 1e-14 the hardest 24^3 blocks stall for 50 steps before the test trips; 1e-2
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(BPB) void bc_update(PcArgs a, int it) {
     const unsigned live = block_live(a, s0, w);
     if (!live) return;
     const int64_t nd = a.nd;
-    const int sp = a.split[s0];
+    const int sp = a.split[s0] & 3;
     block_gram<SM>(a.p, a.q, s0, live, nd, acc, red);
     if (threadIdx.x == 0) {
         bool ok = false;
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(BPB) void bc_update(PcArgs a, int it) {
             }
             ok = small_solve(G, Y, nl, kSplitTol, cs);
             if (ok) expand_live(Y, live, w, AL);
-            else a.split[s0] = 1;
+            else a.split[s0] = (a.split[s0] & ~3) | 1;
         }
         if (!ok) {
             // split: alpha_c = rho_cc / (p_c^T q_c); a zero denominator breaks the column down
@@ -574,11 +576,16 @@ __global__ __launch_bounds__(BPB) void bc_dir(PcArgs a, int first) {
     const unsigned live = block_live(a, s0, w);
     if (!live) return;
     const int64_t nd = a.nd;
-    const int sp = a.split[s0];
+    const int sv = a.split[s0], sp = sv & 3;
+    const bool shrank = (unsigned(sv >> 2) & ~live) != 0u;   // columns converged since
     block_gram<SM>(a.r, a.z, s0, live, nd, acc, red);
     if (threadIdx.x == 0 && !first) {
         bool ok = false;
-        if (sp == 0) {
+        int state = sp;
+        if (sp == 0 && shrank) {
+            for (int e = 0; e < LDW * LDW; ++e) BE[e] = double2{0.0, 0.0};   // restart
+            ok = true;
+        } else if (sp == 0) {
             const int nl = compact_acc<SM>(acc, live, Y);
             int r = 0;
             for (int c = 0; c < w; ++c) {
@@ -607,10 +614,12 @@ __global__ __launch_bounds__(BPB) void bc_dir(PcArgs a, int first) {
                     }
                 }
             } else {
-                a.split[s0] = 2;   // restart: p = z
+                state = 2;   // restart: p = z
             }
         }
+        a.split[s0] = state | int(live << 2);
     }
+    if (threadIdx.x == 0 && first) a.split[s0] = int(live << 2);
     if (threadIdx.x == 0)
         for (int c = 0; c < SM; ++c)
             for (int d = 0; d < SM; ++d)
