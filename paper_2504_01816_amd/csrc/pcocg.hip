@@ -270,7 +270,7 @@ constexpr int LDW = kMaxBlockWidth;
 // splits (at 1e-14 the hardest 24^3 blocks stall for 50 steps before the test trips; 1e-2
 // splits blocks that would converge).
 constexpr double kSplitTol = 1e-3;
-constexpr int BPB = 256;    // threads per block-COCG workgroup (one block per workgroup)
+constexpr int BPB = 1024;   // threads per block-COCG workgroup (one block per workgroup)
 
 __device__ __forceinline__ double2 cmul(double2 u, double2 v) {
     return double2{u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x};
@@ -1016,21 +1016,21 @@ hipError_t run_block(const PcocgLaunch& L, PcArgs& a, dim3 grid, Step& step, int
     a.boff = L.boff;
     a.split = L.split;
     if (!L.kron) a.z = a.r;
-    const dim3 bgrid(unsigned(L.nblk)), block(BPB);
+    const dim3 bgrid(unsigned(L.nblk)), bblock(BPB);
     const int sm = L.width <= 2 ? 2 : (L.width <= 4 ? 4 : 8);
     auto update = [&](int it) {
-        if (sm == 2) hipLaunchKernelGGL(bc_update<2>, bgrid, block, 0, s, a, it);
-        else if (sm == 4) hipLaunchKernelGGL(bc_update<4>, bgrid, block, 0, s, a, it);
-        else hipLaunchKernelGGL(bc_update<8>, bgrid, block, 0, s, a, it);
+        if (sm == 2) hipLaunchKernelGGL(bc_update<2>, bgrid, bblock, 0, s, a, it);
+        else if (sm == 4) hipLaunchKernelGGL(bc_update<4>, bgrid, bblock, 0, s, a, it);
+        else hipLaunchKernelGGL(bc_update<8>, bgrid, bblock, 0, s, a, it);
         return hipGetLastError();
     };
     auto dir = [&](int first) {
-        if (sm == 2) hipLaunchKernelGGL(bc_dir<2>, bgrid, block, 0, s, a, first);
-        else if (sm == 4) hipLaunchKernelGGL(bc_dir<4>, bgrid, block, 0, s, a, first);
-        else hipLaunchKernelGGL(bc_dir<8>, bgrid, block, 0, s, a, first);
+        if (sm == 2) hipLaunchKernelGGL(bc_dir<2>, bgrid, bblock, 0, s, a, first);
+        else if (sm == 4) hipLaunchKernelGGL(bc_dir<4>, bgrid, bblock, 0, s, a, first);
+        else hipLaunchKernelGGL(bc_dir<8>, bgrid, bblock, 0, s, a, first);
         return hipGetLastError();
     };
-    hipLaunchKernelGGL(pc_start, grid, block, 0, s, a);
+    hipLaunchKernelGGL(pc_start, grid, dim3(PB), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (L.kron && (e = apply_precond(L, prefix, s)) != hipSuccess) return e;
