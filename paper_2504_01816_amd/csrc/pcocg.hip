@@ -516,6 +516,10 @@ __global__ __launch_bounds__(BPB) void bc_update(PcArgs a, int it) {
     double nrm[SM];
     for (int c = 0; c < SM; ++c) nrm[c] = 0.0;
     for (int64_t i = threadIdx.x; i < nd; i += BPB) {
+        // an offset the compiler cannot see through keeps the coefficient reads (broadcast
+        // LDS loads) inside the loop instead of holding SM x SM of them in registers
+        int o = 0;
+        asm volatile("" : "+v"(o));
         double2 pv[SM], qv[SM];
 #pragma unroll
         for (int k = 0; k < SM; ++k)
@@ -532,7 +536,7 @@ __global__ __launch_bounds__(BPB) void bc_update(PcArgs a, int it) {
 #pragma unroll
             for (int k = 0; k < SM; ++k)
                 if (live >> k & 1u) {
-                    const double2 al = AL[k * LDW + c];
+                    const double2 al = AL[o + k * LDW + c];
                     const double2 t = cmul(pv[k], al), u = cmul(qv[k], al);
                     dx.x += t.x;
                     dx.y += t.y;
@@ -628,6 +632,8 @@ __global__ __launch_bounds__(BPB) void bc_dir(PcArgs a, int first) {
                         double2{acc[2 * (c * SM + d)], acc[2 * (c * SM + d) + 1]};
     __syncthreads();
     for (int64_t i = threadIdx.x; i < nd; i += BPB) {
+        int o = 0;   // keeps the coefficient reads inside the loop (as in bc_update)
+        asm volatile("" : "+v"(o));
         double2 pv[SM];
         if (!first) {
 #pragma unroll
@@ -646,7 +652,7 @@ __global__ __launch_bounds__(BPB) void bc_dir(PcArgs a, int first) {
 #pragma unroll
                 for (int k = 0; k < SM; ++k)
                     if (live >> k & 1u) {
-                        const double2 t = cmul(pv[k], BE[k * LDW + c]);
+                        const double2 t = cmul(pv[k], BE[o + k * LDW + c]);
                         v.x += t.x;
                         v.y += t.y;
                     }
