@@ -1,8 +1,9 @@
 """GPU parity of block COCG (options.cocg_block: the systems of one orbital and one frequency
 solved as blocks with a shared Krylov space, with or without the Kronecker preconditioner)
 against the oracle's block COCG and its plain DFPT, element by element: widths 2, 3, 4 and 8,
-ragged blocks, chunked launches, an isolated box, a zero column and the iteration cap, the
-batched-frequency energy with its backward, and the 24^3 cell against the plain solver."""
+ragged blocks, chunked launches, an isolated box, a zero column and the iteration cap, equal
+trial vectors (split blocks), the batched-frequency energy with its backward, row-slab steps
+with the GEMM preconditioner passes, and the 24^3 cell against the plain solver."""
 import numpy as np
 import pytest
 import torch
@@ -169,3 +170,21 @@ def test_block_cell24_matches_single_system_solver(width, pre):
     say("iterations single %d block %d" % (st_a["cocg_iters_total"], st_b["cocg_iters_total"]))
     assert rc_a == 0 and rc_b == 0
     assert rel(b.cpu().numpy(), a.cpu().numpy()) < 1e-7
+
+
+def test_block_on_row_slabs_and_gemm_preconditioner():
+    # a 36x36x12 cell: the plane exceeds one workgroup, so q = A p runs on row slabs, and the
+    # axes beyond 32 points take the Kronecker GEMM passes of the preconditioner; two chunks
+    c = synth._cell_from_seed((36, 36, 12), 0.45, 3, 3, 37, device=DEV)
+    dc = api.device_cell(c, DEV)
+    ns = c.psi.shape[0]
+    say("block chi0 36x36x12 (row slabs, GEMM preconditioner passes), width 3, two chunks")
+    U = np.random.default_rng(48).standard_normal((5, c.nd))
+    out, rc, st = api.rpa_apply_chi0(dc, 0.3, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-12, cocg_block=3, flags=PRE,
+                                          max_systems=3 * ns))
+    assert rc == 0 and st["cocg_launches"] == 2
+    for j0, j1 in ((0, 3), (3, 5)):
+        ref, it_ref, _ = chi0_apply_block(U[j0:j1].T, c.vloc, c.psi.T, c.eps, 0.3, c.shape, c.h,
+                                          1e-12, 5000, 3, precond=True)
+        assert rel(out[j0:j1].cpu().numpy().T, ref) < 1e-9
