@@ -21,22 +21,21 @@ so the block shrinks as its columns converge; columns with b = 0 are never live.
 shrinks, the block restarts on its remaining columns (beta = 0, P_L = Z_L): the directions
 kept from the larger block are no longer conjugate within the smaller one, and on the 24^3
 cell keeping them leaves single columns at 76-124 steps where their blocks converged in
-20-24 (with the restart: 23-24).  The small
-systems are solved by Gaussian elimination with partial pivoting after scaling every row,
-then every column, to a largest modulus of one (the entries of rho and P^T Q scale with the
-residual norms of their columns, which differ by up to the tolerance ratio once some columns
-near convergence), and a pivot of modulus <= split_tol = 1e-3 of the scaled matrix means
-the block has lost rank: the residual columns of a block can become linearly dependent
-before they converge (on the 24^3 cell, three columns of a block of four reach rank one and
-stall long before their tolerance; splitting at 1e-14 instead of 1e-3 left the hardest
-blocks at 76-84 iterations instead of 26-28, and 1e-2 splits blocks that would converge).
-The block then splits: each of its live columns goes on as single-vector (P)COCG from its
-current x and r.  A failed alpha solve takes that step with the per-column alpha_c = rho_cc / (p_c^T q_c),
-and the next direction step restarts every column with p_c = z_c (beta = 0); a failed beta
-solve restarts at once.  A split column with a zero p_c^T q_c or r_c^T z_c breaks down.
-The iteration count of a column is the number of products with A it took part in.  Groups
-are runs of trial vectors with equal frequency, cut into blocks of at most `width`
-consecutive vectors from the start of each run.
+20-24 (with the restart: 23-24).  The small systems are solved by Gaussian elimination with
+partial pivoting after scaling every row, then every column, to a largest modulus of one
+(the entries of rho and P^T Q scale with the residual norms of their columns, which differ
+by up to the tolerance ratio once some columns near convergence).  A pivot of modulus
+<= split_tol = 1e-3 of the scaled matrix means the block has lost rank (its residual columns
+have become nearly linearly dependent); the block then splits: each of its live columns
+goes on as single-vector (P)COCG from its current x and r.  A failed alpha solve takes that
+step with the per-column alpha_c = rho_cc / (p_c^T q_c), and the next direction step
+restarts every column with p_c = z_c (beta = 0); a failed beta solve restarts at once.  A
+split column with a zero p_c^T q_c or r_c^T z_c breaks down.  (Without the restart on
+deflation, a split at 1e-14 left the hardest 24^3 blocks at 76-84 steps and 1e-3 at 26-28;
+with the restart no block of that cell splits at either threshold; 1e-2 split blocks that
+would converge.)  The iteration count of a column is the number of products with A it took
+part in.  Groups are runs of trial vectors with equal frequency, cut into blocks of at most
+`width` consecutive vectors from the start of each run.
 """
 import numpy as np
 

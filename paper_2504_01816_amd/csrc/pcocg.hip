@@ -267,8 +267,7 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
 // and beta), restarting with p = z at the next direction step.
 constexpr int LDW = kMaxBlockWidth;
 // Pivot threshold of the scaled small solves below which a block counts as rank deficient and
-// splits (at 1e-14 the hardest 24^3 blocks stall for 50 steps before the test trips; 1e-2
-// splits blocks that would converge).
+// splits (a condition number beyond ~1e3 after scaling; 1e-2 splits blocks that converge).
 constexpr double kSplitTol = 1e-3;
 constexpr int BPB = 1024;   // threads per block-COCG workgroup (one block per workgroup)
 
