@@ -669,10 +669,13 @@ __global__ __launch_bounds__(BPB) void bc_dir(PcArgs a, int first) {
 // inverse z transform of 64 z-pencils in LDS (results of the forward transform in
 // registers); inverse y and x transforms per plane.  The dense 1D transforms cost n LDS
 // multiply-adds per point and axis, so the fused passes beat the MFMA GEMM passes only for
-// short axes (measured: 1.25x faster at 24^3, 2.5x slower at 48^3); used for n0, n1, n2 <= 32.
+// short axes (measured on the whole solve: 1.25x faster than the GEMM passes at 24^3, before
+// the forward x basis was stored transposed, which took the solve from 368 to 313 ms; 118
+// against 70 s at 48^3 after it); used for n0, n1, n2 <= 32.
 constexpr int kFusedMaxXY = 32;
 constexpr int kFusedMaxZ = 32;
 constexpr int kPencils = 64;
+constexpr size_t kMaxLds = 160 * 1024;   // LDS of one workgroup on gfx950
 constexpr int kZr = 64 / (PB / kPencils);   // z values per thread in the pencil pass (n2 <= 64)
 
 // forward (INV = false): c_(a,b) = sum_(x,y) Ux[x + n0 a] Uy[y + n1 b] f_(x,y); inverse: the
@@ -977,19 +980,23 @@ hipError_t launch_vloc_mean(int64_t nd, const double* vloc, double* out, hipStre
 // Kronecker GEMM passes.
 hipError_t apply_precond(const PcocgLaunch& L, int nsys, hipStream_t s) {
     const Grid& g = L.g;
-    // RPA_PRECOND_PASSES=gemm forces the GEMM passes (for measurements)
+    // RPA_PRECOND_PASSES=gemm forces the GEMM passes, =lds the fused passes wherever their
+    // LDS and the pencil pass's z range allow (for measurements)
     static const char* force = std::getenv("RPA_PRECOND_PASSES");
-    const bool fits = g.n0 <= kFusedMaxXY && g.n1 <= kFusedMaxXY && g.n2 <= kFusedMaxZ &&
-                      nsys <= 65535;
-    const bool gemm = !fits || (force && std::strcmp(force, "gemm") == 0);
-    if (gemm)
-        return launch_kron_precond(g, nsys, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky, L.kz,
-                                   L.kshift, s);
     const int P = g.n0 * g.n1;
     const int64_t nd = g.nd();
     const size_t lxy = size_t(2 * P) * sizeof(double2) +
                        size_t(g.n0 * g.n0 + g.n1 * g.n1) * sizeof(double);
     const size_t lz = size_t(g.n2 * kPencils) * sizeof(double2) + size_t(g.n2 * g.n2) * sizeof(double);
+    const bool can = g.n2 <= kZr * (PB / kPencils) && lxy <= kMaxLds && lz <= kMaxLds &&
+                     nsys <= 65535;
+    const bool fits = can && g.n0 <= kFusedMaxXY && g.n1 <= kFusedMaxXY && g.n2 <= kFusedMaxZ;
+    const bool lds = (force && std::strcmp(force, "lds") == 0) ? can
+                   : (force && std::strcmp(force, "gemm") == 0) ? false
+                   : fits;
+    if (!lds)
+        return launch_kron_precond(g, nsys, L.r, L.z, L.tmp, L.Ux, L.Uy, L.Uz, L.kx, L.ky, L.kz,
+                                   L.kshift, s);
     hipError_t e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(pc_xy<false>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lxy))) != hipSuccess)
