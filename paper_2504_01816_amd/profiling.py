@@ -61,6 +61,10 @@ def cmd_apply(args):
 
     wl = _workload(args)
     c = wl.cells[0]
+    if args.box:
+        # the isolated-box counterpart of the workload's cell: same grid, spacing and
+        # occupied count, 16 seeded wells inside a Dirichlet box
+        c = synth.box_cell(c.shape, c.h, 16, c.n_occ, 101)
     dc = api.device_cell(c, "cuda:0")
     nvec = args.nvec or wl.n_r[0]
     X = api.rpa_apply_coulomb(dc, torch.tensor(wl.V0[0][:nvec], device="cuda:0"), 1)
@@ -82,7 +86,7 @@ def cmd_apply(args):
             tot[k] += st[k]
     torch.cuda.synchronize()
     tot.update(workload=wl.name, precision=args.precision, nvec=nvec, omegas=list(idx),
-               precond=bool(args.precond), block=args.block)
+               precond=bool(args.precond), block=args.block, box=bool(args.box))
     print(json.dumps(tot), file=sys.stderr)
     if args.out:
         with open(args.out, "w") as f:
@@ -273,6 +277,8 @@ def main():
                    help="preconditioned COCG (Kronecker shifted-Laplacian preconditioner)")
     a.add_argument("--block", type=int, default=0,
                    help="block COCG width (options.cocg_block; 0: single systems)")
+    a.add_argument("--box", action="store_true",
+                   help="an isolated (Dirichlet) box of the workload's grid instead of its cell")
     ss = sub.add_parser("subspace")
     ss.add_argument("--gen-device", action="store_true")
     ss.add_argument("--config", type=int, default=2)
