@@ -27,6 +27,9 @@
 // Layout: r, p, z, q as N_d x 2 nsys real columns (real, imaginary part of slot t in columns
 // 2t, 2t+1), rho, b2, active and the preconditioner shifts per slot; x, the right-hand
 // sides, iteration counts and statuses per system, x and b complex interleaved, nsys x N_d.
+// The same buffers and kernels serve block COCG (options.cocg_block, the block variant of the
+// solver that Sec. 3 names with the preconditioner): the step stores q only and block
+// kernels, one workgroup per block of slots, take the place of the scalar recurrences.
 #include <cstdlib>
 #include <cstring>
 #include <vector>
