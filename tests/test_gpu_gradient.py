@@ -73,6 +73,6 @@ def test_autograd_binding_matches_backward():
     E = api.RPAEnergy.apply(v, dc, 6, om, W, V0, opts)
     (2.5 * E).backward()
     res = api.rpa_energy(dc, 6, om, W, [V0], opts, save=True)
-    assert abs(float(E) - res["E_c"][0]) <= 1e-14 * abs(res["E_c"][0])
+    assert abs(float(E.detach()) - res["E_c"][0]) <= 1e-14 * abs(res["E_c"][0])
     g, _, _ = api.rpa_energy_backward(dc, om, W, res["Vsave"][0], res["Csave"][0], 2.5, opts)
     assert torch.allclose(v.grad, g, rtol=1e-12, atol=0.0)
