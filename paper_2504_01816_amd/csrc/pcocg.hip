@@ -209,9 +209,11 @@ __global__ __launch_bounds__(PB) void pc_step(PcArgs a, int it) {
     }
 }
 
+constexpr int RZB = 1024;   // threads of pc_rz (a streaming pass: more waves in flight)
+
 // rho' = r^T z; first: p = z, else p = z + (rho'/rho) p; rho = rho'.
-__global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
-    __shared__ double red[(PB / 64) * 4];
+__global__ __launch_bounds__(RZB) void pc_rz(PcArgs a, int first) {
+    __shared__ double red[(RZB / 64) * 4];
     const int s = blockIdx.x;
     if (!a.active[s]) return;
     const int64_t nd = a.nd;
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
     double* pr = a.p + nd * (2 * int64_t(s));
     double* pi = pr + nd;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};   // rho' re/im, |r|^2, |z|^2
-    for (int64_t i = threadIdx.x; i < nd; i += PB) {
+    for (int64_t i = threadIdx.x; i < nd; i += RZB) {
         const double a0 = rr[i], a1 = ri[i], c0 = zr[i], c1 = zi[i];
         acc[0] += a0 * c0 - a1 * c1;
         acc[1] += a0 * c1 + a1 * c0;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(PB) void pc_rz(PcArgs a, int first) {
         br = (acc[0] * rho.x + acc[1] * rho.y) / rr2;
         bi = (acc[1] * rho.x - acc[0] * rho.y) / rr2;
     }
-    for (int64_t i = threadIdx.x; i < nd; i += PB) {
+    for (int64_t i = threadIdx.x; i < nd; i += RZB) {
         const double o0 = first ? 0.0 : pr[i], o1 = first ? 0.0 : pi[i];
         pr[i] = zr[i] + br * o0 - bi * o1;
         pi[i] = zi[i] + br * o1 + bi * o0;
@@ -1140,7 +1142,7 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = precond()) != hipSuccess) return e;
-    hipLaunchKernelGGL(pc_rz, grid, block, 0, s, a, 1);
+    hipLaunchKernelGGL(pc_rz, grid, dim3(RZB), 0, s, a, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::vector<int> act(L.nsys);
     for (int it = 1; it <= L.max_iter; ++it) {
@@ -1157,7 +1159,7 @@ hipError_t launch_pcocg(const PcocgLaunch& L, hipStream_t s) {
         }
         if (it == L.max_iter) break;
         if ((e = precond()) != hipSuccess) return e;
-        hipLaunchKernelGGL(pc_rz, grid, block, 0, s, a, 0);
+        hipLaunchKernelGGL(pc_rz, grid, dim3(RZB), 0, s, a, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
