@@ -681,7 +681,8 @@ constexpr int kFusedMaxXY = 32;
 constexpr int kFusedMaxZ = 32;
 constexpr int kPencils = 64;
 constexpr size_t kMaxLds = 160 * 1024;   // LDS of one workgroup on gfx950
-constexpr int kZr = 64 / (PB / kPencils);   // z values per thread in the pencil pass (n2 <= 64)
+constexpr int ZB = 512;                      // threads of the pencil pass
+constexpr int kZr = 64 / (ZB / kPencils);   // z values per thread in the pencil pass (n2 <= 64)
 
 // forward (INV = false): c_(a,b) = sum_(x,y) Ux[x + n0 a] Uy[y + n1 b] f_(x,y); inverse: the
 // transposed bases.  grid (n2, systems), in/out: N_d x 2 nsys split columns.
@@ -740,24 +741,24 @@ __global__ __launch_bounds__(PB) void pc_xy(const double* in, double* out, int n
 
 // In place on the x-y mode coefficients: forward z transform, division by
 // 1/2 (kx + ky + kz) + sigma_t - i omega_t, inverse z transform.  grid (ceil(P/64), systems).
-__global__ __launch_bounds__(PB) void pc_zscale(double* data, int n0, int n1, int n2, int64_t nd,
+__global__ __launch_bounds__(ZB) void pc_zscale(double* data, int n0, int n1, int n2, int64_t nd,
                                                 const double* Uz, const double* kx,
                                                 const double* ky, const double* kz,
                                                 const double2* kshift) {
     extern __shared__ double2 shz[];
     const int P = n0 * n1;
     const int g0 = blockIdx.x * kPencils, t = blockIdx.y;
-    const int j = threadIdx.x % kPencils, cg = threadIdx.x / kPencils, ng = PB / kPencils;
+    const int j = threadIdx.x % kPencils, cg = threadIdx.x / kPencils, ng = ZB / kPencils;
     double2* Pz = shz;                                          // n2 x 64
     double* uz = reinterpret_cast<double*>(shz + n2 * kPencils);
     double* dr = data + nd * (2 * int64_t(t));
     double* di = dr + nd;
-    for (int e = threadIdx.x; e < n2 * kPencils; e += PB) {
+    for (int e = threadIdx.x; e < n2 * kPencils; e += ZB) {
         const int zz = e / kPencils, xy = g0 + (e - zz * kPencils);
         Pz[e] = (xy < P) ? double2{dr[xy + int64_t(P) * zz], di[xy + int64_t(P) * zz]}
                          : double2{0.0, 0.0};
     }
-    for (int i = threadIdx.x; i < n2 * n2; i += PB) uz[i] = Uz[i];
+    for (int i = threadIdx.x; i < n2 * n2; i += ZB) uz[i] = Uz[i];
     __syncthreads();
     double2 acc[kZr];
 #pragma unroll
@@ -993,7 +994,7 @@ hipError_t apply_precond(const PcocgLaunch& L, int nsys, hipStream_t s) {
     const size_t lxy = size_t(2 * P) * sizeof(double2) +
                        size_t(g.n0 * g.n0 + g.n1 * g.n1) * sizeof(double);
     const size_t lz = size_t(g.n2 * kPencils) * sizeof(double2) + size_t(g.n2 * g.n2) * sizeof(double);
-    const bool can = g.n2 <= kZr * (PB / kPencils) && lxy <= kMaxLds && lz <= kMaxLds &&
+    const bool can = g.n2 <= kZr * (ZB / kPencils) && lxy <= kMaxLds && lz <= kMaxLds &&
                      nsys <= 65535;
     const bool fits = can && g.n0 <= kFusedMaxXY && g.n1 <= kFusedMaxXY && g.n2 <= kFusedMaxZ;
     const bool lds = (force && std::strcmp(force, "lds") == 0) ? can
@@ -1016,7 +1017,7 @@ hipError_t apply_precond(const PcocgLaunch& L, int nsys, hipStream_t s) {
                        L.tmp, g.n0, g.n1, nd, L.Ux, L.Uy);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(pc_zscale, dim3(unsigned((P + kPencils - 1) / kPencils), unsigned(nsys)),
-                       dim3(PB), lz, s, L.tmp, g.n0, g.n1, g.n2, nd, L.Uz, L.kx, L.ky, L.kz,
+                       dim3(ZB), lz, s, L.tmp, g.n0, g.n1, g.n2, nd, L.Uz, L.kx, L.ky, L.kz,
                        L.kshift);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(pc_xy<true>, dim3(unsigned(g.n2), unsigned(nsys)), dim3(PB), lxy, s, L.tmp,
