@@ -682,12 +682,13 @@ constexpr int kFusedMaxZ = 32;
 constexpr int kPencils = 64;
 constexpr size_t kMaxLds = 160 * 1024;   // LDS of one workgroup on gfx950
 constexpr int ZB = 512;                      // threads of the pencil pass
+constexpr int XYB = 512;                     // threads of the plane passes
 constexpr int kZr = 64 / (ZB / kPencils);   // z values per thread in the pencil pass (n2 <= 64)
 
 // forward (INV = false): c_(a,b) = sum_(x,y) Ux[x + n0 a] Uy[y + n1 b] f_(x,y); inverse: the
 // transposed bases.  grid (n2, systems), in/out: N_d x 2 nsys split columns.
 template <bool INV>
-__global__ __launch_bounds__(PB) void pc_xy(const double* in, double* out, int n0, int n1,
+__global__ __launch_bounds__(XYB) void pc_xy(const double* in, double* out, int n0, int n1,
                                             int64_t nd, const double* Ux, const double* Uy) {
     extern __shared__ double2 shx[];
     const int P = n0 * n1;
@@ -698,16 +699,16 @@ __global__ __launch_bounds__(PB) void pc_xy(const double* in, double* out, int n
     double* uy = ux + n0 * n0;
     const double* ir = in + nd * (2 * int64_t(t)) + int64_t(z) * P;
     const double* ii = ir + nd;
-    for (int i = threadIdx.x; i < P; i += PB) A[i] = double2{ir[i], ii[i]};
+    for (int i = threadIdx.x; i < P; i += XYB) A[i] = double2{ir[i], ii[i]};
     // x basis stored so that lanes (consecutive a) read consecutive entries: ux[a + n0 k] =
     // U[a + n0 k] for the inverse, U[k + n0 a] (the transpose) for the forward transform
-    for (int i = threadIdx.x; i < n0 * n0; i += PB) {
+    for (int i = threadIdx.x; i < n0 * n0; i += XYB) {
         const int a = i % n0, k = i / n0;
         ux[i] = INV ? Ux[i] : Ux[k + n0 * a];
     }
-    for (int i = threadIdx.x; i < n1 * n1; i += PB) uy[i] = Uy[i];
+    for (int i = threadIdx.x; i < n1 * n1; i += XYB) uy[i] = Uy[i];
     __syncthreads();
-    for (int o = threadIdx.x; o < P; o += PB) {          // along x
+    for (int o = threadIdx.x; o < P; o += XYB) {          // along x
         const int y = o / n0, a = o - y * n0;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < n0; ++k) {
@@ -719,7 +720,7 @@ __global__ __launch_bounds__(PB) void pc_xy(const double* in, double* out, int n
         B[o] = double2{sr, si};
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < P; o += PB) {          // along y
+    for (int o = threadIdx.x; o < P; o += XYB) {          // along y
         const int b = o / n0, x = o - b * n0;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < n1; ++k) {
@@ -733,7 +734,7 @@ __global__ __launch_bounds__(PB) void pc_xy(const double* in, double* out, int n
     __syncthreads();
     double* orr = out + nd * (2 * int64_t(t)) + int64_t(z) * P;
     double* oi = orr + nd;
-    for (int i = threadIdx.x; i < P; i += PB) {
+    for (int i = threadIdx.x; i < P; i += XYB) {
         orr[i] = A[i].x;
         oi[i] = A[i].y;
     }
@@ -1013,14 +1014,14 @@ hipError_t apply_precond(const PcocgLaunch& L, int nsys, hipStream_t s) {
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(pc_zscale),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lz))) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(pc_xy<false>, dim3(unsigned(g.n2), unsigned(nsys)), dim3(PB), lxy, s, L.r,
+    hipLaunchKernelGGL(pc_xy<false>, dim3(unsigned(g.n2), unsigned(nsys)), dim3(XYB), lxy, s, L.r,
                        L.tmp, g.n0, g.n1, nd, L.Ux, L.Uy);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(pc_zscale, dim3(unsigned((P + kPencils - 1) / kPencils), unsigned(nsys)),
                        dim3(ZB), lz, s, L.tmp, g.n0, g.n1, g.n2, nd, L.Uz, L.kx, L.ky, L.kz,
                        L.kshift);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(pc_xy<true>, dim3(unsigned(g.n2), unsigned(nsys)), dim3(PB), lxy, s, L.tmp,
+    hipLaunchKernelGGL(pc_xy<true>, dim3(unsigned(g.n2), unsigned(nsys)), dim3(XYB), lxy, s, L.tmp,
                        L.z, g.n0, g.n1, nd, L.Ux, L.Uy);
     return hipGetLastError();
 }
