@@ -99,6 +99,32 @@ def test_rank_deficient_block_splits_into_single_vector_solves():
     assert np.all(np.abs(it - it1) <= 2)
 
 
+def test_deflation_restarts_the_block_on_the_remaining_columns():
+    # column 0 is an eigenvector of A, so the first block step solves it exactly and it
+    # leaves the block; the other columns then go on as a fresh block solve of their current
+    # residuals (beta = 0): the whole run equals one capped step followed by a new solve
+    rng = np.random.default_rng(8)
+    N = 36
+    S = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    S = 0.5 * (S + S.T)
+    Qr, _ = np.linalg.qr(rng.standard_normal((N, N)))          # real orthogonal: Q^T Q = I
+    lam = 2.0 + 0.3j + rng.uniform(0.0, 1.5, N)
+    A = Qr @ np.diag(lam) @ Qr.T + 0.05 * S                      # complex symmetric
+    w, V = np.linalg.eig(A)
+    B = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+    B[:, 0] = V[:, 0]
+    X, it, st = bcocg(lambda P: A @ P, B, 1e-10, 200)
+    assert np.all(st == OK) and it[0] == 1
+    X1, _, _ = bcocg(lambda P: A @ P, B, 1e-10, 1)
+    R1 = B[:, 1:] - A @ X1[:, 1:]
+    # block COCG commutes with scaling the columns (B D gives X D), so scaling each residual
+    # column to its right-hand side's norm makes one relative tolerance the per-column test
+    D = np.linalg.norm(B[:, 1:], axis=0) / np.linalg.norm(R1, axis=0)
+    Y, it2, st2 = bcocg(lambda P: A @ P, R1 * D[None, :], 1e-10, 200)
+    assert np.all(st2 == OK) and np.all(np.abs(it[1:] - (1 + it2)) <= 1)
+    np.testing.assert_allclose(X[:, 1:], X1[:, 1:] + Y / D[None, :], rtol=1e-8, atol=1e-10)
+
+
 def test_iteration_cap_reports_not_converged():
     rng = np.random.default_rng(5)
     A = _sym(rng, 40, 0.3 + 0.01j)
