@@ -3,7 +3,8 @@ solved as blocks with a shared Krylov space, with or without the Kronecker preco
 against the oracle's block COCG and its plain DFPT, element by element: widths 2, 3, 4 and 8,
 ragged blocks, chunked launches, an isolated box, a zero column and the iteration cap, equal
 trial vectors (split blocks), the batched-frequency energy with its backward, row-slab steps
-with the GEMM preconditioner passes, and the 24^3 cell against the plain solver."""
+with the GEMM preconditioner passes, the gathered step where no march shape fits, and the
+24^3 cell against the plain solver."""
 import numpy as np
 import pytest
 import torch
@@ -188,3 +189,25 @@ def test_block_on_row_slabs_and_gemm_preconditioner():
         ref, it_ref, _ = chi0_apply_block(U[j0:j1].T, c.vloc, c.psi.T, c.eps, 0.3, c.shape, c.h,
                                           1e-12, 5000, 3, precond=True)
         assert rel(out[j0:j1].cpu().numpy().T, ref) < 1e-9
+
+
+def test_gathered_step_on_a_plane_no_march_shape_fits():
+    # a 37x37 plane fits neither one workgroup (1369 columns) nor equal row slabs (37 is
+    # prime), so q = A p takes the gathered step kernel; single-system and block solves
+    c = synth._cell_from_seed((37, 37, 12), 0.45, 3, 3, 53, device=DEV)
+    dc = api.device_cell(c, DEV)
+    say("preconditioned and block chi0 on 37x37x12 (gathered step)")
+    U = np.random.default_rng(49).standard_normal((3, c.nd))
+    from oracle import precond as opre
+    out, rc, st = api.rpa_apply_chi0(dc, 0.4, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-12, flags=PRE))
+    ref, it_ref, _ = opre.chi0_apply_precond(U.T, c.vloc, c.psi.T, c.eps, 0.4, c.shape, c.h,
+                                             1e-12, 5000)
+    assert rc == 0 and rel(out.cpu().numpy().T, ref) < 1e-9
+    assert abs(st["cocg_iters_total"] - int(it_ref.sum())) <= it_ref.size
+    out, rc, st = api.rpa_apply_chi0(dc, 0.4, torch.tensor(U, device=DEV),
+                                     dict(cocg_tol=1e-12, flags=PRE, cocg_block=3))
+    ref, it_ref, _ = chi0_apply_block(U.T, c.vloc, c.psi.T, c.eps, 0.4, c.shape, c.h, 1e-12,
+                                      5000, 3, precond=True)
+    assert rc == 0 and rel(out.cpu().numpy().T, ref) < 1e-9
+    assert iters_close(st, it_ref)
