@@ -47,6 +47,11 @@ extern "C" {
 /* ---------------------------------------------------------------- status codes */
 #define RPA_OK            0
 #define RPA_ENOTCONV      1   /* warning: some COCG system hit cocg_max_iter; results written */
+#define RPA_ESUBCAP       2   /* warning: with ec_tol > 0, some frequency stopped at
+                                 subspace_iters before its energy test held (Algorithm 1's
+                                 epsilon_c test); results written, rpa_stats.subspace_capped
+                                 counts those frequencies.  When RPA_ENOTCONV also holds, the
+                                 call returns RPA_ENOTCONV. */
 #define RPA_EINVAL       -1   /* bad argument (size, pointer, non-finite scalar, unsorted eps) */
 #define RPA_EWORKSPACE   -2   /* workspace missing, misaligned or smaller than required */
 #define RPA_EBREAKDOWN   -3   /* COCG bilinear form vanished before convergence */
@@ -146,7 +151,10 @@ typedef struct rpa_stats {
     int32_t fp64_fallbacks;       /* RPA_MIXED: systems that reached cocg_max_iter in complex64
                                      and were solved on in FP64 from where they stopped (up
                                      to cocg_max_iter further iterations) */
-    int32_t reserved;             /* 0 */
+    int32_t subspace_capped;      /* frequencies whose subspace iteration stopped at
+                                     subspace_iters with ec_tol > 0 before
+                                     |E_k - E_{k-1}| <= ec_tol |E_k| held (the energy
+                                     reported is that of the last iterate) */
 } rpa_stats;
 
 /* Library version (major*10000 + minor*100 + patch). */

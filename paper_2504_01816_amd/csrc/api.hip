@@ -118,6 +118,8 @@ int check_geometry(const rpa_cell* c) {
     if (nd > (int64_t(1) << 26)) return fail(RPA_EINVAL, "grid larger than 2^26 points");
     if (int64_t(c->n[0]) * c->n[1] > 4096)
         return fail(RPA_EINVAL, "x-y plane larger than 4096 points");
+    if (c->n[0] > 1024 || c->n[1] > 1024 || c->n[2] > 1024)
+        return fail(RPA_EINVAL, "every axis must have at most 1024 points");
     if (!(c->h > 0.0) || !std::isfinite(c->h)) return fail(RPA_EINVAL, "h must be finite and > 0");
     if (c->n_occ < 1 || c->n_occ > 128 || c->n_occ >= nd)
         return fail(RPA_EINVAL, "n_occ must be in [1, 128] and below N_d");
@@ -139,6 +141,19 @@ int check_cell(const rpa_cell* c) {
 }
 
 Grid grid_of(const rpa_cell* c) { return Grid{c->n[0], c->n[1], c->n[2], c->h, c->bc}; }
+
+// The plain COCG kernel marches the x-y plane whole (at most 3072 points) or in row slabs of
+// at least 12 rows; grids that fit neither are solved only by the host-driven solvers
+// (RPA_FLAG_PRECOND or cocg_block >= 2), whose step kernel has a gathered fallback.
+int check_solver_geometry(const rpa_cell* c, const Opts& o) {
+    if (o.host_driven()) return RPA_OK;
+    if (!cocg_shape_exists(grid_of(c), o.precision == RPA_MIXED))
+        return fail(RPA_EINVAL, "no COCG launch shape fits this grid: the x-y plane exceeds "
+                                "3072 points and n[1] has no divisor giving row slabs of at "
+                                "least 12 rows and at most 1024 points (the preconditioned or "
+                                "block solver accepts it)");
+    return RPA_OK;
+}
 
 int check_ws(void* ws, size_t ws_bytes, size_t need) {
     if (need == 0) return RPA_OK;
@@ -432,6 +447,7 @@ int coulomb_apply(const Grid& g, const CoulombBuf& b, int power, int nvec, const
 struct SolveTally {
     int64_t iters_total = 0, systems = 0, launches = 0, refinements = 0;
     int iters_max = 0, unconv = 0, breakdown = 0, fallbacks = 0;
+    int subcap = 0;   // frequencies stopped at subspace_iters before the energy test held
     double kernel_ms = 0.0, point_iters = 0.0;
 };
 
@@ -503,6 +519,7 @@ void add_stats(rpa_stats* st, const SolveTally& t) {
     st->cocg_kernel_ms += t.kernel_ms;
     st->cocg_point_iters += t.point_iters;
     st->fp64_fallbacks += t.fallbacks;
+    st->subspace_capped += t.subcap;
 }
 
 // Dispatch order of the ns*nv systems of a chunk: the previous apply's iteration counts when
@@ -786,7 +803,27 @@ int solve_status(const SolveTally& t) {
         set_error(std::to_string(t.unconv) + " COCG system(s) hit cocg_max_iter");
         return RPA_ENOTCONV;
     }
+    if (t.subcap) {
+        set_error(std::to_string(t.subcap) + " frequency(ies) stopped at subspace_iters before "
+                  "the energy test held");
+        return RPA_ESUBCAP;
+    }
     return RPA_OK;
+}
+
+// Algorithm 1's stopping test after subspace iteration k at one frequency: a fixed count when
+// ec_tol <= 0, else |E_k - E_{k-1}| <= ec_tol |E_k| (k >= 2) or the cap.  *capped is set when
+// the cap stops an iteration whose energy test has not held.
+bool subspace_stop(const Opts& o, int k, double E, double Eprev, bool* capped) {
+    *capped = false;
+    if (o.ec_tol <= 0.0) return k >= o.subspace_iters;
+    const bool met = k >= 2 && std::fabs(E - Eprev) <= o.ec_tol * std::fabs(E);
+    if (met) return true;
+    if (k >= o.subspace_iters) {
+        *capped = true;
+        return true;
+    }
+    return false;
 }
 
 // Orthonormalise R into V: M = R^T R = L L^T, V = R L^{-T}.
@@ -845,19 +882,18 @@ int subspace_iter(const rpa_cell* cell, const Grid& g, double omega, double weig
                 return fail(RPA_EBREAKDOWN, "COCG breakdown in " + std::to_string(t.breakdown) +
                                                 " system(s); I - C not positive definite");
             if (t.unconv)
-                return fail(RPA_ENOTCONV < 0 ? RPA_ENOTCONV : RPA_ENOTPD,
-                            std::to_string(t.unconv) + " COCG system(s) hit cocg_max_iter; "
-                            "I - C not positive definite");
+                return fail(RPA_ENOTPD, std::to_string(t.unconv) + " COCG system(s) hit "
+                                        "cocg_max_iter; I - C not positive definite");
             return fail(info != 0 ? RPA_ENOTPD : RPA_EINVAL,
                         info != 0 ? "I - C is not positive definite" : "non-finite subspace energy");
         }
         if (V_saved) RPA_HIP(launch_copy(nd * nr, V, V_saved, s));
         if (C_out) RPA_HIP(launch_copy(int64_t(nr) * nr, b.C, C_out, s));
         RPA_CHECK(chol_orthonormalize(g, nr, b.R, V, b, s));
-        bool stop;
-        if (o.ec_tol <= 0.0) stop = (k >= o.subspace_iters);
-        else stop = (k >= o.subspace_iters) || (k >= 2 && std::fabs(E - Eprev) <= o.ec_tol * std::fabs(E));
+        bool capped = false;
+        const bool stop = subspace_stop(o, k, E, Eprev, &capped);
         Eprev = E;
+        if (capped) t.subcap += 1;
         if (stop) break;
     }
     if (ritz_out) {
@@ -963,11 +999,10 @@ int energy_batched(const rpa_cell* cell, int nr, int nfreq, const double* omega,
             RPA_HIP(launch_gemm_tall_small(nd, nr, b.R + a * blk, b.T + f * sq, b.Vall + f * blk, s));
             E[f] = Ef;
             k[f] += 1;
-            bool stop;
-            if (o.ec_tol <= 0.0) stop = (k[f] >= o.subspace_iters);
-            else stop = (k[f] >= o.subspace_iters) ||
-                        (k[f] >= 2 && std::fabs(Ef - Eprev[f]) <= o.ec_tol * std::fabs(Ef));
+            bool capped = false;
+            const bool stop = subspace_stop(o, k[f], Ef, Eprev[f], &capped);
             Eprev[f] = Ef;
+            if (capped) t.subcap += 1;
             if (!stop) next.push_back(f);
         }
         active.swap(next);
@@ -1140,6 +1175,8 @@ const char* rpa_error_string(int code) {
     switch (code) {
         case RPA_OK: return "ok";
         case RPA_ENOTCONV: return "COCG did not converge within cocg_max_iter (results written)";
+        case RPA_ESUBCAP: return "subspace iteration stopped at subspace_iters before the energy "
+                                 "test held (results written)";
         case RPA_EINVAL: return "invalid argument";
         case RPA_EWORKSPACE: return "workspace missing, misaligned or too small";
         case RPA_EBREAKDOWN: return "COCG breakdown";
@@ -1188,9 +1225,16 @@ int rpa_workspace_size(int32_t op, int32_t ncell, const rpa_cell* cells, const i
         Carver cv;
         switch (op) {
             case RPA_OP_COULOMB: { CoulombBuf b; carve_coulomb(cv, g, nvec[c], b); break; }
-            case RPA_OP_CHI0: { Chi0Buf b; carve_chi0(cv, g, ns, nvec[c], o, false, false, b); break; }
-            case RPA_OP_SUBSPACE: { SubBuf b; carve_sub(cv, g, ns, nvec[c], o, b); break; }
+            case RPA_OP_CHI0: {
+                RPA_CHECK(check_solver_geometry(&cells[c], o));
+                Chi0Buf b; carve_chi0(cv, g, ns, nvec[c], o, false, false, b); break;
+            }
+            case RPA_OP_SUBSPACE: {
+                RPA_CHECK(check_solver_geometry(&cells[c], o));
+                SubBuf b; carve_sub(cv, g, ns, nvec[c], o, b); break;
+            }
             case RPA_OP_ENERGY: {
+                RPA_CHECK(check_solver_geometry(&cells[c], o));
                 if (o.freq_mode == RPA_INDEPENDENT && nfreq < 1)
                     return fail(RPA_EINVAL, "nfreq must be >= 1");
                 if (copt.empty()) {
@@ -1206,6 +1250,7 @@ int rpa_workspace_size(int32_t op, int32_t ncell, const rpa_cell* cells, const i
                 continue;
             }
             case RPA_OP_BACKWARD: {
+                RPA_CHECK(check_solver_geometry(&cells[c], o));
                 if (nfreq < 1) return fail(RPA_EINVAL, "nfreq must be >= 1");
                 BackBuf b; carve_back(cv, g, ns, nvec[c], o, b); break;
             }
@@ -1248,6 +1293,7 @@ int rpa_apply_chi0(const rpa_cell* cell, double omega, int32_t nvec, const doubl
     if (in == out) return fail(RPA_EINVAL, "in and out must not overlap");
     Opts o;
     RPA_CHECK(read_opts(opt, &o));
+    RPA_CHECK(check_solver_geometry(cell, o));
     const Grid g = grid_of(cell);
     Carver dry;
     Chi0Buf b;
@@ -1278,6 +1324,7 @@ int rpa_subspace_iter(const rpa_cell* cell, double omega, double weight, int32_t
     if (!V || !ec_out) return fail(RPA_EINVAL, "V and ec_out are required");
     Opts o;
     RPA_CHECK(read_opts(opt, &o));
+    RPA_CHECK(check_solver_geometry(cell, o));
     Carver dry;
     SubBuf b;
     carve_sub(dry, g, cell->n_occ, nr, o, b);
@@ -1313,6 +1360,7 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
     RPA_CHECK(read_opts(opt, &o));
     for (int c = 0; c < ncell; ++c) {
         RPA_CHECK(check_cell(&cells[c]));
+        RPA_CHECK(check_solver_geometry(&cells[c], o));
         const Grid g = grid_of(&cells[c]);
         if (nr[c] < 1 || nr[c] > 4096 || nr[c] > g.nd())
             return fail(RPA_EINVAL, "nr must be in [1, min(4096, N_d)]");
@@ -1357,6 +1405,7 @@ int rpa_energy(int32_t ncell, const rpa_cell* cells, const int32_t* nr, int32_t 
         t.kernel_ms += r.t.kernel_ms;
         t.point_iters += r.t.point_iters;
         t.fallbacks += r.t.fallbacks;
+        t.subcap += r.t.subcap;
         if (stats) {
             stats->chi0_applies += r.applies;
             stats->subspace_iters_total += r.applies;
@@ -1390,6 +1439,7 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
     if (!std::isfinite(grad_ec)) return fail(RPA_EINVAL, "grad_ec must be finite");
     Opts o;
     RPA_CHECK(read_opts(opt, &o));
+    RPA_CHECK(check_solver_geometry(cell, o));
     Carver dry;
     BackBuf b;
     carve_back(dry, g, cell->n_occ, nr, o, b);

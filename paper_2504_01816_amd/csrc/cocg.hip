@@ -160,7 +160,38 @@ Chosen choose(const Grid& g, bool mixed, bool xcomplex, bool allow_forced) {
     return best;
 }
 
+// The geometric part of choose(): some compiled variant fits the grid's plane (block size,
+// slab height, halo threads, LDS), whatever its register use.
+bool geometry_fits(const Grid& g, const cocg::Variant& v) {
+    if (g.n2 % v.Z != 0) return false;
+    const int s_lo = v.slab ? 2 : 1, s_hi = v.slab ? g.n1 / 12 : 1;
+    for (int nslab = s_lo; nslab <= s_hi; ++nslab) {
+        if (g.n1 % nslab != 0) continue;
+        const int rows = g.n1 / nslab;
+        const int ps = rows * g.n0;
+        const int bs = ((ps + v.C - 1) / v.C + 63) / 64 * 64;
+        if (bs > v.bsmax) continue;
+        if (v.slab && 12 * g.n0 > bs) continue;
+        if (lds_bytes(g.n0, rows, v.Z, 1) > 150 * 1024) continue;
+        return true;
+    }
+    return false;
+}
+
 }  // namespace
+
+bool cocg_shape_exists(const Grid& g, bool mixed) {
+    int nv = 0;
+    const cocg::Variant* tab = cocg::f64_variants(&nv);
+    bool f64 = false, mx = !mixed;
+    for (int k = 0; k < nv; ++k) {
+        const cocg::Variant& v = tab[k];
+        if (v.occ != 0 || !geometry_fits(g, v)) continue;
+        f64 = true;
+        if (mixed && cocg::mixed_variant(v.C, v.Z, v.bsmax, v.occ, v.slab)) mx = true;
+    }
+    return f64 && mx;
+}
 
 hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     if (L.nsys <= 0) return hipSuccess;

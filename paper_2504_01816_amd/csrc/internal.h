@@ -163,6 +163,10 @@ struct CocgLaunch {
                            // starts at the true residual b - A x
 };
 hipError_t launch_cocg(const CocgLaunch& a, hipStream_t s);
+// Host-only: whether the batched COCG kernel has a launch shape for this grid (a whole-plane
+// variant of at most 3 columns per thread and 1024 threads, or row slabs of at least 12 rows
+// with one column per thread), in FP64 and, with `mixed`, also in complex64.  No device call.
+bool cocg_shape_exists(const Grid& g, bool mixed);
 
 // Delta rho epilogue: out[r, j] = 4 sum_n psi[r,n] Re x[n + ns*j][r]; x is float64 with
 // `stride` doubles per point (1: real parts only, 2: complex interleaved)

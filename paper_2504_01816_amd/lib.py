@@ -10,7 +10,7 @@ from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RPA_LIB_PATH") or os.path.join(HERE, "librpa_gfx950.so")
 
-RPA_OK, RPA_ENOTCONV = 0, 1
+RPA_OK, RPA_ENOTCONV, RPA_ESUBCAP = 0, 1, 2
 RPA_EINVAL, RPA_EWORKSPACE, RPA_EBREAKDOWN, RPA_ENOTPD, RPA_EHIP, RPA_ENOTIMPL = -1, -2, -3, -4, -5, -6
 RPA_FP64, RPA_MIXED = 0, 1
 RPA_WARM, RPA_INDEPENDENT = 0, 1
@@ -39,7 +39,7 @@ class RpaStats(ctypes.Structure):
                 ("chi0_applies", c_int32), ("subspace_iters_total", c_int32),
                 ("cocg_launches", c_int64), ("cocg_kernel_ms", c_double),
                 ("cocg_point_iters", c_double), ("fp64_fallbacks", c_int32),
-                ("reserved", c_int32)]
+                ("subspace_capped", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -477,6 +477,14 @@ CONFIG_NAMES = {
 }
 
 
+def workload_frequencies(k):
+    """(omega, weight) of workload k without generating its cell: the single node omega = 1
+    with weight 1 for the 12^3 workload, Gauss-Legendre 8 on the rational map otherwise."""
+    if k == 0:
+        return np.array([1.0]), np.array([1.0])
+    return frequency_rule(8, 1.0)
+
+
 def workload(k, tol=1e-10, device=None):
     """The five synthetic workloads.  device: torch device for the ground-state solver of
     the larger cells (None: host)."""
@@ -484,7 +492,7 @@ def workload(k, tol=1e-10, device=None):
         c = _cell_from_seed((12, 12, 12), 0.5, 2, 4, 1, fixed=(2.0, 1.0), tol=tol, device=device)
         return Workload(CONFIG_NAMES[0], [c], [16], np.array([1.0]), np.array([1.0]), 1e-10, 5,
                         [random_block(c.nd, 16, 1001)])
-    om, W = frequency_rule(8, 1.0)
+    om, W = workload_frequencies(k)
     if k == 1:
         c = _cell_from_seed((24, 24, 24), 0.4, 16, 16, 2, tol=tol, device=device)
         return Workload(CONFIG_NAMES[1], [c], [64], om, W, 1e-8, 0, [random_block(c.nd, 64, 1002)])

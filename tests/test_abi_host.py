@@ -77,8 +77,40 @@ def test_defaults_and_error_strings(so):
     o = L.default_options()
     assert o.precision == L.RPA_FP64 and o.cocg_tol == 1e-8 and o.freq_mode == L.RPA_WARM
     assert so.rpa_version() >= 10000
-    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
         assert so.rpa_error_string(code)
+    assert b"unknown" not in so.rpa_error_string(L.RPA_ESUBCAP)
+
+
+def test_grids_without_a_launch_shape_are_rejected_before_device_work(so):
+    # 59 x 59: the plane exceeds 3 columns for each of 1024 threads and 59 rows have no
+    # divisor for row slabs; only the host-driven solvers (gathered step) accept it
+    c = _cell(n=(59, 59, 12))
+    nv = (ctypes.c_int32 * 1)(4)
+    out = ctypes.c_size_t(0)
+    for op in (L.RPA_OP_CHI0, L.RPA_OP_SUBSPACE, L.RPA_OP_ENERGY, L.RPA_OP_BACKWARD):
+        assert so.rpa_workspace_size(op, 1, ctypes.byref(c), nv, 1, None,
+                                     ctypes.byref(out)) == L.RPA_EINVAL
+        assert "launch shape" in L.last_error()
+    assert so.rpa_apply_chi0(ctypes.byref(c), 1.0, 4, 0x3000, 0x4000, None, None, 0x5000,
+                             1 << 30, None) == L.RPA_EINVAL
+    for o in (L.default_options(flags=L.RPA_FLAG_PRECOND), L.default_options(cocg_block=2)):
+        assert so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(c), nv, 1, ctypes.byref(o),
+                                     ctypes.byref(out)) == 0
+    # the Coulomb operator needs no COCG shape
+    assert so.rpa_workspace_size(L.RPA_OP_COULOMB, 1, ctypes.byref(c), nv, 1, None,
+                                 ctypes.byref(out)) == 0
+    # 48 x 64 fits whole-plane (3 columns per thread); 48 x 48 in row slabs
+    for n in ((48, 64, 12), (48, 48, 48), (36, 36, 36), (24, 24, 24)):
+        for prec in (L.RPA_FP64, L.RPA_MIXED):
+            o = L.default_options(precision=prec)
+            assert so.rpa_workspace_size(L.RPA_OP_CHI0, 1, ctypes.byref(_cell(n=n)), nv, 1,
+                                         ctypes.byref(o), ctypes.byref(out)) == 0, (n, prec)
+    # the 1D eigenbasis kernel takes one thread per point: every axis <= 1024
+    c = _cell(n=(7, 7, 1100))
+    assert so.rpa_workspace_size(L.RPA_OP_COULOMB, 1, ctypes.byref(c), nv, 1, None,
+                                 ctypes.byref(out)) == L.RPA_EINVAL
+    assert "1024" in L.last_error()
 
 
 def test_workspace_query_is_host_only_and_monotone(so):

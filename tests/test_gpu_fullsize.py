@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle_pool
 from oracle import chi0 as ochi0
 from oracle import coulomb as ocoul
 from oracle import subspace as osub
@@ -93,6 +94,47 @@ def test_energy_full_24_mixed_within_1e6_of_fp64(wl1, block1):
 
 
 @pytest.mark.slow
+def test_energy_full_24_matches_oracle(wl1, block1):
+    # E_c of the 24^3 workload end to end (warm start, Algorithm 1's order) at the highest and
+    # the lowest frequency of its GL8 rule, two subspace iterations each, against the oracle
+    # run on every host core; COCG tol 1e-11 on both sides, so that the solver difference
+    # (cond(A) tol) stays below the 1e-9 bar of the FP64 path; the mixed path at 1e-6
+    c = wl1.cells[0]
+    dc, _ = block1
+    pick = [0, 7]
+    om, W = wl1.omegas[pick], wl1.weights[pick]
+    tol, its = 1e-11, 2
+    V0 = torch.tensor(wl1.V0[0], device=DEV)
+    o = dict(cocg_tol=tol, subspace_iters=its, ec_tol=0.0, cocg_max_iter=20000)
+    say("24^3 E_c on the GPU, FP64 and mixed")
+    e64 = api.rpa_energy(dc, 64, om, W, [V0], o)
+    emx = api.rpa_energy(dc, 64, om, W, [V0], dict(o, precision=MIXED))
+    assert e64["status"] == 0 and emx["status"] == 0
+    say("24^3 E_c by the oracle (%d workers)" % oracle_pool.n_workers())
+    psi = c.psi.T.copy()
+    V = osub.chol_orthonormalize(wl1.V0[0].T.copy())
+    Eref = []
+    with oracle_pool.pool() as ex:
+        for m in range(len(pick)):
+            def apply(Vb, m=m):
+                U = ocoul.nu_apply(Vb, c.shape, c.h, 1)
+                D, it, st = oracle_pool.chi0_apply(ex, U, c.vloc, psi, c.eps, float(om[m]),
+                                                   c.shape, c.h, tol, 20000)
+                assert np.all(st == 0)
+                return ocoul.nu_apply(D, c.shape, c.h, 1), dict(iters=it)
+            out = osub.subspace_iteration(apply, V, float(W[m]), its)
+            Eref.append(out["E"])
+            V = out["V_next"]
+    Eref = np.array(Eref)
+    say("E_freq oracle %s\n       fp64 %s\n      mixed %s" % (Eref, e64["E_freq"][0],
+                                                             emx["E_freq"][0]))
+    np.testing.assert_array_less(np.abs(e64["E_freq"][0] - Eref), 1e-9 * np.abs(Eref))
+    assert abs(e64["E_c"][0] - Eref.sum()) <= 1e-9 * abs(Eref.sum())
+    assert abs(emx["E_c"][0] - Eref.sum()) <= 1e-6 * abs(Eref.sum())
+    np.testing.assert_array_equal(e64["iters"][0], [its, its])
+
+
+@pytest.mark.slow
 def test_chi0_full_block_48_sampled_column():
     say("generating the 48^3 workload")
     wl = synth.workload(2, device=DEV)
@@ -111,6 +153,46 @@ def test_chi0_full_block_48_sampled_column():
         assert rel(out[pick].cpu().numpy().T, ref) < 1e-8
         del out
         torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_chi0_full_block_48_low_frequency_column_both_precisions():
+    # the 48^3 block of 256 trial vectors at its second-lowest GL8 frequency (omega = 0.113, a
+    # hard end of the spectrum whose oracle column still finishes in about a minute on the
+    # host cores; at 0.0203 it takes twice that), in the bench's launch configuration: the
+    # row-slab kernel's long solves in FP64 and in the mixed path, where an iteration cap of
+    # 400 makes the hardest complex64 systems stop and finish by the FP64 continuation from
+    # x_hi and the exact residual; tol 1e-10 on every side, compared at 1e-6 (cond(A) tol)
+    say("generating the 48^3 workload")
+    wl = synth.workload(2, device=DEV)
+    c = wl.cells[0]
+    dc = api.device_cell(c, DEV)
+    U = api.rpa_apply_coulomb(dc, torch.tensor(wl.V0[0], device=DEV), 1)
+    m, j, tol = 6, 77, 1e-10
+    om = float(wl.omegas[m])
+    u = U[j].cpu().numpy()
+    got = {}
+    for precision, cap in ((0, 20000), (MIXED, 400)):
+        say("48^3 chi0 block of 256 at omega %.4g precision %d cap %d" % (om, precision, cap))
+        out, rc, st = api.rpa_apply_chi0(dc, om, U, dict(cocg_tol=tol, precision=precision,
+                                                         cocg_max_iter=cap))
+        say("status %d, iterations %d (max %d), FP64 continuations %d" % (
+            rc, st["cocg_iters_total"], st["cocg_iters_max"], st["fp64_fallbacks"]))
+        assert rc == 0 and st["cocg_systems"] == 256 * 64 and st["n_unconverged"] == 0
+        if precision == MIXED:
+            assert st["fp64_fallbacks"] > 0
+        got[precision] = out[j].cpu().numpy()
+        del out
+        torch.cuda.empty_cache()
+    say("oracle column %d at 48^3 (%d workers)" % (j, oracle_pool.n_workers()))
+    with oracle_pool.pool() as ex:
+        ref, it, st = oracle_pool.chi0_column(ex, u, c.vloc, np.ascontiguousarray(c.psi.T),
+                                              c.eps, om, c.shape, c.h, tol, 20000)
+    say("oracle iterations per orbital: max %d, total %d" % (it.max(), it.sum()))
+    assert np.all(st == 0)
+    for precision, v in got.items():
+        say("precision %d: relative difference %.3e" % (precision, rel(v, ref)))
+        assert rel(v, ref) < 1e-6
 
 
 @pytest.mark.slow

@@ -39,3 +39,22 @@ def test_device_ground_state_matches_host():
     assert r1.max() < 1e-9 and r2.max() < 1e-9
     np.testing.assert_allclose(e2, e1, rtol=0, atol=1e-11)
     np.testing.assert_allclose(np.abs(X2 @ X1.T), np.eye(6), atol=1e-8)
+
+
+def test_workload_frequency_rule_equals_the_oracle_quadrature():
+    # the frequencies and weights every workload feeds to both sides come from synth; they must
+    # be the oracle's pinned Gauss-Legendre rule on the map omega = omega0 (1+t)/(1-t), bit for
+    # bit, for every size the tests and the bench use (an error in synth's copy would
+    # otherwise pass parity, since both sides would integrate with the same wrong nodes)
+    from oracle import quadrature
+    for n in (1, 2, 3, 8, 16):
+        for w0 in (1.0, 0.5):
+            om, W = synth.frequency_rule(n, w0)
+            om_ref, W_ref = quadrature.frequency_grid(n, w0)
+            np.testing.assert_array_equal(om, om_ref)
+            np.testing.assert_array_equal(W, W_ref)
+    for k in (1, 2, 3, 4):
+        wl = synth.workload_frequencies(k)
+        om_ref, W_ref = quadrature.frequency_grid(8, 1.0)
+        np.testing.assert_array_equal(wl[0], om_ref)
+        np.testing.assert_array_equal(wl[1], W_ref)
