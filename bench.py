@@ -1,19 +1,22 @@
 """Benchmark of the RPA chi0 hot path on one MI355X.
 
-A step is one pass of the whole hot path on the 24^3 workload (16 Gaussian wells,
-N_s = 16, N_r = 64, 8 Gauss-Legendre frequencies, COCG tol 1e-8): rpa_energy over all
-frequencies (subspace iteration stopping at a relative energy change of 1e-8, at most 50
-iterations per frequency) and then rpa_energy_backward (one chi0 block-apply per
-frequency).  By default the frequencies are batched (every frequency starts from V0 and all
-frequencies still iterating share one COCG launch per subspace iteration) in FP64;
---freq-mode warm runs Algorithm 1's warm-started sequence instead.  Inputs are synthetic,
-seeded and resident in HBM before the timed region.
+Default (--mode cycle): the 48^3 workload (64 Gaussian wells on a jittered lattice, N_s = 64,
+N_r = 256, 8 Gauss-Legendre frequencies, COCG tol 1e-8), complex64 COCG state with float64
+reliable updates.  A step is one pass of the hot path at one frequency: one subspace
+iteration (u = nu^{1/2} V, chi0 u by the projector and 16384 batched Sternheimer solves,
+Delta rho, R = nu^{1/2} chi0 u, the projected matrix and its Rayleigh-Ritz energy, Cholesky-QR)
+through rpa_subspace_iter; step k works on frequency k mod 8, every frequency keeping its own
+block (the independent-frequency schedule, frequency by frequency).  `value` is chi0
+block-applies per second over the timed steps.  After them, time-to-E_c is measured with
+rpa_energy at a fixed number of subspace iterations per frequency, in the mixed path and in
+the FP64 path on the same inputs ("compare": the metric's FP32-refined vs FP64).
 
-Printed: one JSON line with the metric (chi0 block-applies per second over the timed
-steps), time-to-E_c, the roofline of the dominant kernel (batched COCG) measured with
-HIP events on its own stream, the same path with complex64 state and float64 reliable
-updates (one warm-up, one timed step: "compare"), and the CPU oracle timed on a bounded
-sample.
+--mode energy: a step is rpa_energy over all frequencies plus rpa_energy_backward (the
+24^3 workload's form; relative energy test, optional preconditioned or block COCG).
+
+Inputs are synthetic, seeded and resident in HBM before the timed region.  Printed: one JSON
+line with the metric, the roofline of the dominant kernel (batched COCG) measured with HIP
+events on its own stream, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -45,10 +48,22 @@ def host_driven_bytes(precond, block, shape):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1, help="workload index (0..4)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="cycle", choices=["cycle", "energy"],
+                    help="cycle: a step is one subspace iteration at one frequency, frequencies "
+                         "in turn; energy: a step is rpa_energy (+ backward)")
+    ap.add_argument("--config", type=int, default=None,
+                    help="workload index (0..4); default 2 (48^3) in cycle mode, 1 (24^3) in "
+                         "energy mode")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default mixed in cycle mode, fp64 in energy mode")
+    ap.add_argument("--refine-tol", type=float, default=0.0,
+                    help="mixed: relative residual drop between reliable updates (0: library "
+                         "default)")
+    ap.add_argument("--ec-iters", type=int, default=1,
+                    help="cycle mode: fixed subspace iterations per frequency of the "
+                         "time-to-E_c runs")
     ap.add_argument("--freq-mode", default="independent", choices=["warm", "independent"],
                     help="warm: frequencies in sequence, each started from the previous one's "
                          "subspace (Algorithm 1); independent: every frequency from V0, all "
@@ -67,10 +82,17 @@ def parse():
     ap.add_argument("--max-systems", type=int, default=0,
                     help="cap on COCG systems per launch (0: the library's memory budget)")
     ap.add_argument("--max-subspace", type=int, default=50)
+    ap.add_argument("--cells-sequential", action="store_true",
+                    help="energy mode, several cells: one rpa_energy call per cell, one after "
+                         "another, instead of one call running the cells concurrently")
     ap.add_argument("--compare", default="other", choices=["none", "other"],
-                    help="other: after the timed steps, also time one step (after one warm-up) "
-                         "of the same path in the other precision")
-    return ap.parse_args()
+                    help="other: also time the same path in the other precision")
+    args = ap.parse_args()
+    if args.config is None:
+        args.config = 2 if args.mode == "cycle" else 1
+    if args.precision is None:
+        args.precision = "mixed" if args.mode == "cycle" else "fp64"
+    return args
 
 
 def cocg_traffic(workload, precision, point_iters_per_launch):
@@ -119,13 +141,228 @@ def cpu_baseline(wl):
                                        float(np.mean(times)))}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only; --gpus %d is not supported (sharding the "
-              "Sternheimer systems across GPUs is described in the design notes, not "
-              "implemented)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def _oracle_orbitals(job):
+    """Worker: the oracle's Sternheimer solves (its right-hand sides, its COCG, its stencil) for
+    some orbitals of one trial vector; returns their iteration counts."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import chi0 as ochi0
+    from oracle import cocg as ococg
+    from oracle import fd as ofd
+
+    u, vloc, psi, eps, om, shape, h, tol, orbs = job
+    bp, _ = ochi0.build_rhs(u[:, None], psi, h ** 3)
+    shifts = np.asarray(eps)[orbs] + 1j * om
+    _, it, _ = ococg.cocg_batched(lambda v: ofd.hamiltonian_apply(v, vloc, shape, h), shifts,
+                                  -bp[:, orbs], tol, 5000)
+    return int(it.sum())
+
+
+def cpu_baseline_parallel(wl, U0, sys_iters_per_apply, omegas_idx=(0, 1)):
+    """The oracle's Sternheimer solves for one trial vector (all N_s orbitals, dealt to worker
+    processes round-robin) at the highest frequencies, timed on every usable host core (at most
+    16); its rate in system-iterations per second, divided into the COCG system-iterations of
+    one chi0 block-apply that the FP64 GPU path measured on the same workload, gives the
+    oracle's (extrapolated) block-applies per second."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    c = wl.cells[0]
+    ns = c.n_occ
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    psi = np.ascontiguousarray(c.psi.T)
+    groups = [list(range(w, ns, cores)) for w in range(min(cores, ns))]
+    total_it, wall = 0, 0.0
+    with ProcessPoolExecutor(max_workers=len(groups), mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(abs, range(len(groups))))          # workers started before the clock
+        for m in omegas_idx:
+            jobs = [(U0, c.vloc, psi, c.eps, float(wl.omegas[m]), c.shape, c.h, wl.cocg_tol, g)
+                    for g in groups]
+            t0 = time.perf_counter()
+            total_it += sum(ex.map(_oracle_orbitals, jobs))
+            wall += time.perf_counter() - t0
+    rate = total_it / wall
+    return {"value": rate / sys_iters_per_apply, "unit": "chi0 block-applies/s", "cores": len(groups),
+            "kind": "oracle",
+            "sample": "trial vector 0 (all %d Sternheimer systems, one worker process per core, "
+                      "orbitals dealt round-robin) at omega = %s: %d COCG system-iterations in "
+                      "%.1f s = %.1f per s; extrapolated to a block-apply by the FP64 GPU path's "
+                      "mean of %.4g system-iterations per block-apply over the 8 frequencies "
+                      "(projector and nu^1/2 not included)" % (
+                          ns, ", ".join("%.4g" % wl.omegas[m] for m in omegas_idx), total_it,
+                          wall, rate, sys_iters_per_apply)}
+
+
+def run_cycle(args):
+    import torch
+
+    from paper_2504_01816_amd import api, synth
+    from paper_2504_01816_amd import lib as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    wl = synth.workload(args.config, device=dev)      # ground state on the GPU (untimed)
+    c = wl.cells[0]
+    dc = api.device_cell(c, dev)
+    nr, nf = wl.n_r[0], len(wl.omegas)
+    print("[bench] workload %s generated in %.1f s" % (wl.name, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    # input preparation (untimed): the orthonormal start block, one copy per frequency
+    Q, _ = torch.linalg.qr(torch.tensor(wl.V0[0], device=dev).T)
+    Vs = [Q.T.contiguous() for _ in range(nf)]
+    del Q
+    prec = {"fp64": L.RPA_FP64, "mixed": L.RPA_MIXED}
+
+    def opts(p):
+        o = dict(precision=prec[p], cocg_tol=wl.cocg_tol, subspace_iters=1, ec_tol=0.0)
+        if args.refine_tol > 0:
+            o["refine_tol"] = args.refine_tol
+        return o
+
+    def step(k):
+        m = k % nf
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = api.rpa_subspace_iter(dc, float(wl.omegas[m]), float(wl.weights[m]), Vs[m],
+                                  opts(args.precision), want_ritz=False, want_saved=False)
+        torch.cuda.synchronize()
+        st = r["stats"]
+        st["wall_s"] = time.perf_counter() - a
+        st["m"] = m
+        st["E"] = r["E"]
+        st["status"] = r["status"]
+        return st
+
+    warm_steps = []
+    for k in range(args.warmup):
+        s = step(k)
+        warm_steps.append(s)
+        print("[bench] warmup %d: omega %.4g, %.2f s, COCG %.0f ms, iterations %d (max %d)" % (
+            k, wl.omegas[s["m"]], s["wall_s"], s["cocg_kernel_ms"], s["cocg_iters_total"],
+            s["cocg_iters_max"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T0 = time.perf_counter()
+    steps = []
+    for k in range(args.warmup, args.warmup + args.steps):
+        s = step(k)
+        steps.append(s)
+        print("[bench] step %d: omega %.4g, %.2f s, COCG %.0f ms, iterations %d (max %d), "
+              "reliable updates %d, FP64 continuations %d, E_m %.12e" % (
+                  k, wl.omegas[s["m"]], s["wall_s"], s["cocg_kernel_ms"], s["cocg_iters_total"],
+                  s["cocg_iters_max"], s["refinements"], s["fp64_fallbacks"], s["E"]),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - T0
+    applies = sum(s["chi0_applies"] for s in steps)
+    # the dominant kernel is the batched COCG of the step's precision; a mixed step below
+    # mixed_min_omega runs the FP64 kernel instead, and a step with FP64 continuations adds FP64
+    # launches: the roofline takes the steps whose one launch is the precision's own kernel
+    min_om = L.default_options().mixed_min_omega if args.precision == "mixed" else 0.0
+
+    def runs_own(s):
+        return wl.omegas[s["m"]] >= min_om
+
+    def own(s):
+        return runs_own(s) and s["cocg_launches"] == 1 and s["fp64_fallbacks"] == 0
+
+    rsteps = [s for s in steps if own(s)]
+    n_before = sum(1 for s in warm_steps if runs_own(s))
+    n_timed = sum(1 for s in steps if runs_own(s))
+    cocg_ms = sum(s["cocg_kernel_ms"] for s in rsteps)
+    pit = sum(s["cocg_point_iters"] for s in rsteps)
+    launches = len(rsteps)
+    alg_pp = ALG_BYTES[args.precision]
+    achieved = alg_pp * pit / (cocg_ms * 1e-3) / 1e9 if cocg_ms > 0 else 0.0
+    avg_ms = cocg_ms / max(1, launches)
+    traffic, tb = cocg_traffic(wl.name, args.precision, pit / max(1, launches))
+    per_freq = {}
+    for s in steps:
+        per_freq.setdefault(s["m"], []).append(s["wall_s"])
+    out = {
+        "metric": "chi0 block-applies/s and time-to-E_c, FP32-refined batched vs FP64, 1 GPU",
+        "value": applies / T,
+        "unit": "chi0 block-applies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128" if args.precision == "fp64" else "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(c.shape), "h": c.h, "n_occ": c.n_occ,
+                   "n_r": nr, "n_freq": nf, "cocg_tol": wl.cocg_tol,
+                   "systems_per_block_apply": c.n_occ * nr, "precision": args.precision,
+                   "step": "one subspace iteration (one chi0 block-apply of %d vectors) at "
+                           "frequency step mod %d" % (nr, nf),
+                   "refine_tol": args.refine_tol or L.default_options().refine_tol,
+                   "mixed_min_omega": L.default_options().mixed_min_omega},
+        "step_ms_per_frequency": {"%.4g" % wl.omegas[m]: 1e3 * float(np.mean(v))
+                                  for m, v in sorted(per_freq.items())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "cocg_wg<%s> (batched COCG, one workgroup per system)" % (
+                         "float, float2" if args.precision == "mixed" else "double, double"),
+                     "launches": launches, "avg_launch_ms": avg_ms,
+                     "launch_omegas": ["%.4g" % wl.omegas[s["m"]] for s in rsteps],
+                     # this kernel's dispatches of the timed region within the whole run, in
+                     # dispatch order (to match a kernel trace of the same command)
+                     "dispatch_range": [n_before, n_before + n_timed],
+                     "steps_excluded_for_fp64_continuations": n_timed - launches,
+                     "traffic_bytes_per_point_iter": tb,
+                     "traffic_GBs": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
+                     "alg_bytes_per_point_iter": alg_pp,
+                     "cocg_share_of_step": cocg_ms * 1e-3 / T,
+                     "timing": "HIP events on the launch stream"},
+    }
+    # time-to-E_c: rpa_energy from V0 at a fixed subspace count per frequency, every frequency
+    # from V0 (batched-independent mode), in both precisions on the same inputs
+    del Vs
+    torch.cuda.empty_cache()
+    V0 = torch.tensor(wl.V0[0], device=dev)
+    ec = {}
+    others = [args.precision] + ([p for p in ("mixed", "fp64") if p != args.precision]
+                                 if args.compare == "other" else [])
+    for p in others:
+        o = dict(opts(p), subspace_iters=args.ec_iters, freq_mode=L.RPA_INDEPENDENT)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = api.rpa_energy(dc, nr, wl.omegas, wl.weights, [V0], o)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - a
+        st = r["stats"]
+        ec[p] = dict(time_to_ec_s=t, E_c=float(r["E_c"][0]), status=r["status"],
+                     chi0_block_applies_per_s=st["chi0_applies"] / t,
+                     cocg_iters_total=st["cocg_iters_total"], cocg_iters_max=st["cocg_iters_max"],
+                     fp64_fallbacks=st["fp64_fallbacks"], refinements=st["refinements"],
+                     cocg_alg_GBs=ALG_BYTES[p] * st["cocg_point_iters"] / (st["cocg_kernel_ms"] * 1e-3) / 1e9,
+                     subspace_iters_per_freq=args.ec_iters, E_freq=r["E_freq"][0].tolist())
+        print("[bench] time-to-E_c %s: %.2f s, E_c %.12e, iterations %d (max %d)" % (
+            p, t, ec[p]["E_c"], st["cocg_iters_total"], st["cocg_iters_max"]), file=sys.stderr,
+            flush=True)
+        torch.cuda.empty_cache()
+    out["time_to_ec_s"] = ec[args.precision]["time_to_ec_s"]
+    out["E_c"] = ec[args.precision]["E_c"]
+    out["time_to_ec_runs"] = ec
+    if len(ec) > 1:
+        o_p = others[1]
+        out["compare"] = {
+            "precision": o_p,
+            "time_to_ec_s": ec[o_p]["time_to_ec_s"],
+            "chi0_block_applies_per_s": ec[o_p]["chi0_block_applies_per_s"],
+            "E_c": ec[o_p]["E_c"],
+            "E_c_rel_diff": abs(ec[o_p]["E_c"] - out["E_c"]) / abs(ec[o_p]["E_c"]),
+            "time_to_ec_ratio_main_over_other": out["time_to_ec_s"] / ec[o_p]["time_to_ec_s"],
+            "speedup_main_vs_other": ec[o_p]["time_to_ec_s"] / out["time_to_ec_s"],
+        }
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        ref = ec.get("fp64", ec[args.precision])
+        U0 = api.rpa_apply_coulomb(dc, V0[:1].contiguous(), 1)[0].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline_parallel(wl, U0, ref["cocg_iters_total"] / nf)
+        print("[bench] cpu baseline %.1f s" % (time.perf_counter() - t), file=sys.stderr,
+              flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def run_energy(args):
     import torch
 
     from paper_2504_01816_amd import api, synth
@@ -147,14 +384,30 @@ def main():
                 freq_mode=L.RPA_WARM if args.freq_mode == "warm" else L.RPA_INDEPENDENT)
     if wl.subspace_iters > 0:
         opts.update(subspace_iters=wl.subspace_iters, ec_tol=0.0)
+    if args.refine_tol > 0:
+        opts.update(refine_tol=args.refine_tol)
 
     def step(opts=opts):
         st = {"fwd_s": 0.0, "bwd_s": 0.0, "applies": 0, "cocg_ms": 0.0, "point_iters": 0.0,
               "launches": 0, "iters": None, "E": None}
         torch.cuda.synchronize()
         a = time.perf_counter()
-        res = api.rpa_energy(cells, wl.n_r, wl.omegas, wl.weights, V0, opts,
-                             save=not args.no_backward)
+        if args.cells_sequential and len(cells) > 1:
+            # the cells one after another, each through its own rpa_energy call (the
+            # comparison for the library's concurrent cells)
+            parts = [api.rpa_energy([cc], [nr], wl.omegas, wl.weights, [v], opts,
+                                    save=not args.no_backward)
+                     for cc, nr, v in zip(cells, wl.n_r, V0)]
+            res = {"stats": {k: sum(p["stats"][k] for p in parts)
+                             for k in ("chi0_applies", "cocg_kernel_ms", "cocg_point_iters",
+                                       "cocg_launches")},
+                   "iters": np.concatenate([p["iters"] for p in parts]),
+                   "E_c": np.concatenate([p["E_c"] for p in parts]),
+                   "Vsave": sum((p["Vsave"] or [None] for p in parts), []) if not args.no_backward else None,
+                   "Csave": sum((p["Csave"] or [None] for p in parts), []) if not args.no_backward else None}
+        else:
+            res = api.rpa_energy(cells, wl.n_r, wl.omegas, wl.weights, V0, opts,
+                                 save=not args.no_backward)
         torch.cuda.synchronize()
         b = time.perf_counter()
         st["fwd_s"] = b - a
@@ -279,6 +532,19 @@ def main():
         print("[bench] cpu baseline %.1f s" % (time.perf_counter() - t), file=sys.stderr,
               flush=True)
     print(json.dumps(out), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only; --gpus %d is not supported (sharding the "
+              "Sternheimer systems across GPUs is described in the design notes, not "
+              "implemented)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "cycle":
+        run_cycle(args)
+    else:
+        run_energy(args)
 
 
 if __name__ == "__main__":

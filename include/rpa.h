@@ -106,7 +106,8 @@ typedef struct rpa_options {
     double ec_tol;           /* relative energy threshold |E_k - E_{k-1}| <= ec_tol |E_k|;
                                 <= 0 selects the fixed count; default 1e-8 */
     double refine_tol;       /* RPA_MIXED: relative drop of the complex64 residual between
-                                float64 refinements (reliable updates), default 0.1 */
+                                float64 refinements (reliable updates), at least 8 iterations
+                                apart except at the tolerance and the cap; default 0.3 */
     int32_t max_systems;     /* cap on Sternheimer systems in flight; 0 = as many as keep
                                 the COCG state within 128 GiB (56 B per point and system in
                                 FP64, 64 B mixed), shared by the cells of an rpa_energy call
@@ -132,6 +133,11 @@ typedef struct rpa_options {
                                 Laplacian.  RPA_FP64 only (RPA_ENOTIMPL with RPA_MIXED);
                                 the state is that of RPA_FLAG_PRECOND (112 B per point and
                                 system). */
+    double mixed_min_omega;  /* RPA_MIXED: trial vectors at frequencies below this (Ha) are
+                                solved in FP64 (complex128 state) instead of complex64: near the
+                                real axis the shifts approach the spectrum and the complex64
+                                recurrences need more extra iterations than they save; 0 runs
+                                every frequency in complex64.  Default 0.05. */
 } rpa_options;
 
 /* Counters accumulated by a call (added to the struct's current contents). */

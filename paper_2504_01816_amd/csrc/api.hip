@@ -43,7 +43,19 @@ void fd_weights(double w[7]) {
 
 namespace {
 
-constexpr int kVersion = 10000;
+constexpr int kVersion = 10100;
+
+// RPA_MIXED: frequencies below this (Ha) solve in FP64.  Near the real axis the Sternheimer
+// shifts come close to the spectrum and the complex64 recurrences lose conjugacy: measured on
+// the 48^3 cell, complex64 needs 2.2x the FP64 iterations at omega = 0.0203 (up to 5x for the
+// orbitals next to the gap), more than its per-iteration saving.
+constexpr double kMixedMinOmega = 0.05;
+
+// RPA_MIXED: default relative drop of the complex64 residual that triggers a reliable update.
+// Measured on the 48^3 cell (complex64 at every frequency): 0.3 takes 3-10% less time than 0.1
+// at the three lowest frequencies (fewer iterations lost between updates), 0.01 and 0.001 take
+// more; with the 8-iteration gap the fast systems at high frequency refine no more often.
+constexpr double kRefineTol = 0.3;
 
 struct Opts {
     int precision = RPA_FP64;
@@ -52,7 +64,8 @@ struct Opts {
     int subspace_iters = 50;
     int freq_mode = RPA_WARM;
     double ec_tol = 1e-8;
-    double refine_tol = 1e-1;
+    double refine_tol = kRefineTol;
+    double mixed_min_omega = kMixedMinOmega;
     int max_systems = 0;
     int sq_order = 0;
     double state_budget = 0.0;   // bytes of COCG state per launch when max_systems = 0 (set
@@ -78,6 +91,7 @@ int read_opts(const rpa_options* o, Opts* out) {
         d.freq_mode = o->freq_mode;
         d.ec_tol = o->ec_tol;
         d.refine_tol = o->refine_tol;
+        d.mixed_min_omega = o->mixed_min_omega;
         d.max_systems = o->max_systems;
         d.sq_order = o->sq_order;
         if (o->flags & ~RPA_FLAG_PRECOND) return fail(RPA_EINVAL, "options.flags: unknown bits");
@@ -95,6 +109,8 @@ int read_opts(const rpa_options* o, Opts* out) {
     if (!std::isfinite(d.ec_tol)) return fail(RPA_EINVAL, "options.ec_tol must be finite");
     if (!(d.refine_tol > 0.0 && d.refine_tol < 1.0))
         return fail(RPA_EINVAL, "options.refine_tol must be in (0, 1)");
+    if (!(d.mixed_min_omega >= 0.0) || !std::isfinite(d.mixed_min_omega))
+        return fail(RPA_EINVAL, "options.mixed_min_omega must be finite and >= 0");
     if (d.max_systems < 0) return fail(RPA_EINVAL, "options.max_systems must be >= 0");
     if (d.sq_order < 0 || d.sq_order > 32)
         return fail(RPA_EINVAL, "options.sq_order must be in [0, 32]");
@@ -195,6 +211,7 @@ struct Chi0Buf {
     void* xlo;      // mixed only
     double* rhi;    // mixed only: complex float64 residual
     double* b2;     // mixed only: |b|^2 per system, for the FP64 continuation
+    float* vloc32;  // mixed only: V_loc in float32 for the complex64 sweeps
     int *iters, *status, *refine;
     double* omega_v;  // per trial vector of a chunk: its frequency
     int* order;       // per system of a chunk: dispatch order
@@ -231,6 +248,12 @@ struct Chi0Host {
         hint.assign(size_t(ns) * nvec, -1);
     }
 };
+
+// Mixed precision: fewest COCG iterations between two reliable updates (besides the ones at the
+// tolerance and at the cap).  Fast-converging systems would otherwise refine every two or three
+// iterations (a refine_tol drop per step), each update a float64 sweep of 80 B per point; at
+// low frequency the updates are dozens of iterations apart and the gap does not bind.
+constexpr int kRefineGap = 8;
 
 // COCG state kept in flight when the caller sets no cap: 128 GiB (under half the HBM of one
 // MI355X), enough for every system of a block at 24^3 and 32^3 and for one frequency's block
@@ -291,6 +314,7 @@ void carve_chi0(Carver& cv, const Grid& g, int ns, int nvec, const Opts& o, bool
     b.x = cv.take<char>(size_t(S) * nd * (b.x_complex ? 16 : 8));
     b.rhi = b.mixed ? cv.take<double>(2 * size_t(S) * nd) : nullptr;
     b.b2 = b.mixed ? cv.take<double>(S) : nullptr;
+    b.vloc32 = b.mixed ? cv.take<float>(size_t(nd)) : nullptr;
     b.iters = cv.take<int>(S);
     b.status = cv.take<int>(S);
     b.refine = cv.take<int>(S);
@@ -582,18 +606,30 @@ void block_order(const rpa_cell* cell, int nv, int width, Chi0Host& h) {
     }
 }
 
+// Whether trial vectors at frequency w solve in FP64 although the buffers are mixed.
+bool fp64_in_mixed(const Chi0Buf& b, const Opts& o, double w) {
+    return b.mixed && w < o.mixed_min_omega;
+}
+
 // Solve the Sternheimer systems of the trial vectors j0 .. j0+nv-1 (columns of U, which
-// points at column j0), each at its own frequency h.omega[j].
+// points at column j0), each at its own frequency h.omega[j].  With mixed buffers and
+// fp64_run, the run solves in FP64 inside the mixed state: the complex128 residual goes in
+// r_hi, the two complex128 direction vectors in [r | p_a] and [p_b | x_lo] (as for the
+// continuation of capped systems), the complex solution in x_hi.
 int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Buf& b,
                 const double* U, int64_t j0, int nv, bool x_complex, Chi0Host& h,
-                hipStream_t s) {
+                hipStream_t s, bool fp64_run = false) {
     const int ns = cell->n_occ;
     const int64_t nd = g.nd();
     const double dV = g.h * g.h * g.h;
     RPA_HIP(launch_proj_coeff(nd, ns, nv, dV, cell->psi, U, b.part, b.nsplit, b.coeff, s));
-    if (b.mixed)
+    if (b.mixed && fp64_run) {
+        RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff, b.rhi, nullptr, s));
+    } else if (b.mixed) {
         RPA_HIP(launch_proj_rhs<float>(nd, ns, nv, cell->psi, U, b.coeff,
                                        reinterpret_cast<float*>(b.r), b.rhi, s));
+        RPA_HIP(launch_to_float(nd, cell->v_loc, b.vloc32, s));
+    }
     else
         RPA_HIP(launch_proj_rhs<double>(nd, ns, nv, cell->psi, U, b.coeff,
                                         reinterpret_cast<double*>(b.r), nullptr, s));
@@ -682,10 +718,26 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
     L.iters = b.iters;
     L.status = b.status;
     L.fp32 = b.mixed;
+    if (b.mixed && fp64_run) {
+        L.r = b.rhi;
+        L.pa = b.r;
+        L.pb = b.pb;
+        L.x_complex = true;
+        L.fp32 = false;
+        L.refinements = b.refine;      // written as 0 by the FP64 kernel
+        hipEvent_t e0, e1;
+        RPA_CHECK(timer_events(&e0, &e1));
+        RPA_HIP(hipEventRecord(e0, s));
+        RPA_HIP(launch_cocg(L, s));
+        RPA_HIP(hipEventRecord(e1, s));
+        return RPA_OK;
+    }
     L.xlo = b.xlo;
     L.rhi = b.rhi;
     L.refinements = b.refine;
     L.refine_tol = o.refine_tol;
+    L.refine_gap = kRefineGap;
+    L.vloc32 = b.vloc32;
     L.b2 = b.b2;
     hipEvent_t e0, e1;
     RPA_CHECK(timer_events(&e0, &e1));
@@ -785,13 +837,18 @@ int chi0_apply(const rpa_cell* cell, const Grid& g, int nvec, const double* in, 
     const int64_t nd = g.nd();
     RPA_HIP(hipMemcpyAsync(b.eps, cell->eps, sizeof(double) * ns, hipMemcpyHostToDevice, s));
     RPA_CHECK(precond_setup(cell, g, b, h, s));
-    for (int j0 = 0; j0 < nvec; j0 += b.chunk) {
-        const int nv = std::min(b.chunk, nvec - j0);
-        RPA_CHECK(solve_chunk(cell, g, o, b, in + nd * j0, j0, nv, false, h, s));
+    // launches of at most b.chunk vectors; with mixed buffers a launch also keeps to one
+    // precision (vectors below mixed_min_omega solve in FP64)
+    for (int j0 = 0; j0 < nvec;) {
+        const bool f64 = fp64_in_mixed(b, o, h.omega[j0]);
+        int nv = 1;
+        while (nv < b.chunk && j0 + nv < nvec && fp64_in_mixed(b, o, h.omega[j0 + nv]) == f64) ++nv;
+        RPA_CHECK(solve_chunk(cell, g, o, b, in + nd * j0, j0, nv, false, h, s, f64));
         RPA_CHECK(tally(b, ns * nv, nd, t, h, int64_t(j0) * ns, s));
-        RPA_CHECK(continue_capped(cell, g, o, b, nv, h, t, s));
+        if (!f64) RPA_CHECK(continue_capped(cell, g, o, b, nv, h, t, s));
         RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
                             b.x_complex ? 2 : 1, out + nd * j0, s));
+        j0 += nv;
     }
     return RPA_OK;
 }
@@ -1200,6 +1257,7 @@ int rpa_default_options(rpa_options* opt) {
     opt->freq_mode = d.freq_mode;
     opt->ec_tol = d.ec_tol;
     opt->refine_tol = d.refine_tol;
+    opt->mixed_min_omega = d.mixed_min_omega;
     opt->max_systems = d.max_systems;
     opt->flags = 0;
     opt->sq_order = d.sq_order;
@@ -1469,9 +1527,11 @@ int rpa_energy_backward(const rpa_cell* cell, int32_t nfreq, const double* omega
         RPA_CHECK(coulomb_apply(g, b.cb, 1, nr, b.W, b.U, s));
         for (int j0 = 0; j0 < nr; j0 += b.xb.chunk) {
             const int nv = std::min(b.xb.chunk, nr - j0);
-            RPA_CHECK(solve_chunk(cell, g, o, b.xb, b.U + nd * j0, j0, nv, b.xb.x_complex, h, s));
+            const bool f64 = fp64_in_mixed(b.xb, o, omega[m]);
+            RPA_CHECK(solve_chunk(cell, g, o, b.xb, b.U + nd * j0, j0, nv, b.xb.x_complex, h, s,
+                                  f64));
             RPA_CHECK(tally(b.xb, ns * nv, nd, t, h, int64_t(j0) * ns, s));
-            RPA_CHECK(continue_capped(cell, g, o, b.xb, nv, h, t, s));
+            if (!f64) RPA_CHECK(continue_capped(cell, g, o, b.xb, nv, h, t, s));
             RPA_HIP(launch_grad_accum_d(nd, ns, nv, cell->psi, b.xb.eps, omega[m], b.xb.coeff,
                                         b.xb.dbuf, b.coefk + j0, b.xb.x, false, grad_vloc, s));
         }

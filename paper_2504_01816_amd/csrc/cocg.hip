@@ -213,6 +213,8 @@ hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     a.order = L.order;
     a.tol2 = L.tol * L.tol;
     a.refine2 = L.refine_tol * L.refine_tol;
+    a.refine_gap = L.refine_gap;
+    a.vloc32 = L.vloc32;
     a.max_iter = L.max_iter;
     a.bd_tol = L.fp32 ? 1e-10 : 1e-14;
     a.nd = L.g.nd();

@@ -23,8 +23,9 @@
 //    since the next sweep reads rows that other threads wrote.
 //  * Mixed precision (T = float): r, p and the partial solution x_lo are complex64; the
 //    solution x_hi and the residual r_hi are complex float64.  When the complex64 residual
-//    has dropped by refine_tol since the last update (or reaches the tolerance), a reliable
-//    update (group-wise residual replacement) runs: x_hi += x_lo and r_hi -= A x_lo, with
+//    has dropped by refine_tol since the last update, at least refine_gap iterations after it
+//    (or reaches the tolerance, or the cap), a reliable update (group-wise residual
+//    replacement) runs: x_hi += x_lo and r_hi -= A x_lo, with
 //    A x_lo evaluated in float64 from the exact complex64 values, so r_hi = b - A x_hi holds
 //    to float64 rounding; then r <- complex64(r_hi).  p and the Krylov recurrence continue.
 //    The tolerance test uses |r_hi|.
@@ -46,10 +47,25 @@ template <typename T> struct Cplx;
 template <> struct Cplx<double> { using type = double2; };
 template <> struct Cplx<float> { using type = float2; };
 
+// Arithmetic precision of the COCG recurrences for a state precision T (reductions always
+// accumulate in float64).  The mixed path computes q = A p and the updates in float32 on its
+// complex64 state.  Built with RPA_MIXED_ARITH=double it computes them in float64 from the
+// stored complex64 values instead, rounding only when it stores: measured on the 48^3 cell,
+// that removes about a fifth of the iteration inflation at the lowest frequency (1.70x the
+// FP64 iterations against 2.18x) but costs a quarter more time per iteration (conversions and
+// register spills of the slab variants), a net loss.
+#ifndef RPA_MIXED_ARITH
+#define RPA_MIXED_ARITH float
+#endif
+template <typename T> struct Arith { using type = double; };
+template <> struct Arith<float> { using type = RPA_MIXED_ARITH; };
+
 struct Args {
     int n0, n1, n2, P;
     double cw[7];          // cw[k] = -1/2 w_k / h^2 for k >= 1; cw[0] = -1/2 * 3 w_0 / h^2
     const double* vloc;
+    const float* vloc32;   // mixed: V_loc rounded to float32, read by the float32 sweeps (half
+                           // the bytes; the float32 diagonal rounds anyway); required there
     const double* eps;
     int ns;
     double omega;          // shift of every system when omega_v is null
@@ -57,6 +73,8 @@ struct Args {
     const int* order;      // workgroup b solves system order[b] (a permutation), or null
     double tol2;
     double refine2;        // mixed: refine_tol^2
+    int refine_gap;        // mixed: fewest iterations between two reliable updates (except at
+                           // the tolerance and the cap)
     int max_iter;
     double bd_tol;
     int64_t nd;
@@ -356,7 +374,13 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
             for (int i = 0; i < C; ++i) {
                 if (!cl.valid[i]) continue;
                 const unsigned idx = unsigned((zo + zz) * P + cl.col[i]);
-                const R diag = R(a.cw[0] + ld(a.vloc, idx) - eps_n);
+                // float32 sweeps read the float32 copy of V_loc (the mixed driver always passes
+                // it); the diagonal is a float32 value either way
+                R diag;
+                if constexpr (std::is_same<R, float>::value)
+                    diag = R(a.cw[0] - eps_n) + ld(a.vloc32, idx);
+                else
+                    diag = R(a.cw[0] + ld(a.vloc, idx) - eps_n);
                 const auto q = stencil<R, Q2, NQ, C>(a, L + zz * PL, Q, 6 + zz, i, cl.cx[i],
                                                      cl.cyl[i], diag, om);
                 cent.finish(CC[zz][i], zo + zz, i, Q[6 + zz][i], q);
@@ -376,7 +400,7 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
 struct Empty {};
 
 // ---------------------------------------------------------------- sweep 1 (sigma)
-template <typename T2, int C>
+template <typename T2, int C, typename RA>
 struct LeadPnew {
     struct Buf { T2 r, p; };
     const T2* r; const T2* pa; int P; const int* col; bool first; double dbr, dbi;
@@ -388,10 +412,12 @@ struct LeadPnew {
         b.p = first ? T2{0, 0} : ld(pa, idx);
         return b;
     }
+    // p_new = r + beta p in the arithmetic precision, rounded once to the state precision
     __device__ T2 make(const Buf& b) const {
-        using R = decltype(T2{}.x);
-        const R br_ = R(dbr), bi_ = R(dbi);
-        return T2{b.r.x + br_ * b.p.x - bi_ * b.p.y, b.r.y + br_ * b.p.y + bi_ * b.p.x};
+        using S = decltype(T2{}.x);
+        const RA br_ = RA(dbr), bi_ = RA(dbi);
+        return T2{S(RA(b.r.x) + br_ * RA(b.p.x) - bi_ * RA(b.p.y)),
+                  S(RA(b.r.y) + br_ * RA(b.p.y) + bi_ * RA(b.p.x))};
     }
 };
 template <typename T2, int C>
@@ -400,7 +426,8 @@ struct CentSigma {
     T2* pb; int P; const int* col; bool first;
     double acc[7];   // sigma re/im, |p|^2, |q|^2, rho0 re/im, |r0|^2
     __device__ Buf load(int, int) const { return Buf{}; }
-    __device__ void finish(const Buf&, int z, int i, T2 c, T2 q) {
+    template <typename Q>
+    __device__ void finish(const Buf&, int z, int i, T2 c, Q q) {
         acc[0] += double(c.x) * q.x - double(c.y) * q.y;
         acc[1] += double(c.x) * q.y + double(c.y) * q.x;
         acc[2] += double(c.x) * c.x + double(c.y) * c.y;
@@ -423,8 +450,9 @@ struct LeadLoad {
     __device__ Buf load_at(int z, unsigned gcol) const { return ld(v, unsigned(z * P) + gcol); }
     __device__ T2 make(const Buf& b) const { return b; }
 };
-// x stored as XS (double: real part only, double2: complex FP64, float2: complex64 x_lo)
-template <typename T2, typename XS>
+// x stored as XS (double: real part only, double2: complex FP64, float2: complex64 x_lo);
+// the updates run in the arithmetic precision RA and round once when stored
+template <typename T2, typename XS, typename RA>
 struct CentUpdate {
     struct Buf { T2 r; XS x; };
     T2* r; XS* x; int P; const int* col; bool xzero; double ar, ai;
@@ -436,20 +464,22 @@ struct CentUpdate {
         if (xzero) b.x = XS{}; else b.x = ld(x, idx);
         return b;
     }
-    __device__ void finish(const Buf& bf, int z, int i, T2 c, T2 q) {
-        using R = decltype(T2{}.x);
+    template <typename Q>
+    __device__ void finish(const Buf& bf, int z, int i, T2 c, Q q) {
+        using S = decltype(T2{}.x);
         const unsigned idx = unsigned(z * P + col[i]);
-        const R a_r = R(ar), a_i = R(ai);
-        T2 rv = bf.r;
-        rv.x -= a_r * q.x - a_i * q.y;
-        rv.y -= a_r * q.y + a_i * q.x;
+        const RA a_r = RA(ar), a_i = RA(ai);
+        T2 rv;
+        rv.x = S(RA(bf.r.x) - (a_r * RA(q.x) - a_i * RA(q.y)));
+        rv.y = S(RA(bf.r.y) - (a_r * RA(q.y) + a_i * RA(q.x)));
         st(r, idx, rv);
         XS xv = bf.x;
         if constexpr (std::is_same<XS, double>::value) {
             xv += double(a_r) * c.x - double(a_i) * c.y;
         } else {
-            xv.x += a_r * c.x - a_i * c.y;
-            xv.y += a_r * c.y + a_i * c.x;
+            using XE = decltype(XS{}.x);
+            xv.x = XE(RA(xv.x) + (a_r * RA(c.x) - a_i * RA(c.y)));
+            xv.y = XE(RA(xv.y) + (a_r * RA(c.y) + a_i * RA(c.x)));
         }
         st(x, idx, xv);
         acc[0] += double(rv.x) * rv.x - double(rv.y) * rv.y;
@@ -525,6 +555,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, BSMAX),
                           amdgpu_waves_per_eu(OCC > 0 ? OCC : 1, 8)))
 void cocg_wg(Args a_in) {
     using T2 = typename Cplx<T>::type;
+    using RA = typename Arith<T>::type;
     constexpr bool MIXED = std::is_same<T, float>::value;
     // Dispatch order: the host passes a permutation that starts the systems expected to need
     // the most iterations first (longest-first list scheduling: the easy ones then fill the
@@ -581,7 +612,7 @@ void cocg_wg(Args a_in) {
     }
 
     double rho_re = 0, rho_im = 0, bb = 0, beta_re = 0, beta_im = 0, rr_ref = 0, tgt2 = 0;
-    int it = 0, st = 0, nref = 0;
+    int it = 0, st = 0, nref = 0, it_ref = 0;
     bool xlo_zero = true, xhi_zero = true, done = false;
     bool cold = false;     // the queue was dropped (reliable update): sweep 1 reloads it
     // Queue of the swept vector, carried from sweep to sweep: after sweep 1 it holds planes
@@ -598,7 +629,7 @@ void cocg_wg(Args a_in) {
         if (carry) {
             // warm start of sweep 1 from the queue: p_new = r + beta p on planes -6 .. 5,
             // four planes at a time
-            const T br = T(beta_re), bi = T(beta_im);
+            const RA br = RA(beta_re), bi = RA(beta_im);
 #pragma unroll
             for (int s0 = 0; s0 < 12; s0 += 4) {
                 T2 rw[4][C];
@@ -615,17 +646,17 @@ void cocg_wg(Args a_in) {
 #pragma unroll
                     for (int i = 0; i < C; ++i) {
                         const T2 pv = Q[s0 + s][i];
-                        Q[s0 + s][i] = T2{rw[s][i].x + br * pv.x - bi * pv.y,
-                                          rw[s][i].y + br * pv.y + bi * pv.x};
+                        Q[s0 + s][i] = T2{T(RA(rw[s][i].x) + br * RA(pv.x) - bi * RA(pv.y)),
+                                          T(RA(rw[s][i].y) + br * RA(pv.y) + bi * RA(pv.x))};
                     }
             }
         }
-        LeadPnew<T2, C> l1{r, pa, P, cl.col, first, beta_re, beta_im};
+        LeadPnew<T2, C, RA> l1{r, pa, P, cl.col, first, beta_re, beta_im};
         CentSigma<T2, C> c1{pb, P, cl.col, first, {0, 0, 0, 0, 0, 0, 0}};
         for (int sl = 0; sl < nslab; ++sl) {
             next_slab(sl);
-            march<T, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q,
-                                     carry);
+            march<RA, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q,
+                                      carry);
         }
         slab_sync();
         cold = false;
@@ -657,23 +688,23 @@ void cocg_wg(Args a_in) {
         {
             LeadLoad<T2> l2{pb, P, cl.col};
             if constexpr (MIXED) {
-                CentUpdate<T2, float2> c2{r, reinterpret_cast<float2*>(a.xlo) + off, P, cl.col,
+                CentUpdate<T2, float2, RA> c2{r, reinterpret_cast<float2*>(a.xlo) + off, P, cl.col,
                                           xlo_zero, alpha_re, alpha_im, {0, 0, 0}};
                 for (int sl = 0; sl < nslab; ++sl) {
                     next_slab(sl);
-                    march<T, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2,
-                                             Q, !SLAB && a.periodic != 0);
+                    march<RA, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2,
+                                              Q, !SLAB && a.periodic != 0);
                 }
                 slab_sync();
                 wg_reduce<3>(c2.acc, red);
                 acc2[0] = c2.acc[0]; acc2[1] = c2.acc[1]; acc2[2] = c2.acc[2];
             } else {
-                CentUpdate<T2, XS> c2{r, reinterpret_cast<XS*>(a.x) + off, P, cl.col,
+                CentUpdate<T2, XS, RA> c2{r, reinterpret_cast<XS*>(a.x) + off, P, cl.col,
                                       first && !a.x_accum, alpha_re, alpha_im, {0, 0, 0}};
                 for (int sl = 0; sl < nslab; ++sl) {
                     next_slab(sl);
-                    march<T, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2,
-                                             Q, !SLAB && a.periodic != 0);
+                    march<RA, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l2, c2,
+                                              Q, !SLAB && a.periodic != 0);
                 }
                 slab_sync();
                 wg_reduce<3>(c2.acc, red);
@@ -692,7 +723,8 @@ void cocg_wg(Args a_in) {
                 // reliable update when the complex64 residual fell by refine_tol or hit tol,
                 // and at the iteration cap (so that a stopped solve leaves x_hi and the exact
                 // r_hi = b - A x_hi for an FP64 continuation)
-                if (acc2[2] <= tgt2 || acc2[2] <= a.refine2 * rr_ref || it >= a.max_iter) {
+                if (acc2[2] <= tgt2 || it >= a.max_iter ||
+                    (acc2[2] <= a.refine2 * rr_ref && it - it_ref >= a.refine_gap)) {
                     // drop the carried queue so that its registers are free for this sweep;
                     // the next sweep 1 reloads its first planes from memory
 #pragma unroll
@@ -717,6 +749,7 @@ void cocg_wg(Args a_in) {
                     ++nref;
                     acc2[0] = cr.acc[0]; acc2[1] = cr.acc[1]; acc2[2] = cr.acc[2];
                     rr_ref = acc2[2];
+                    it_ref = it;
                     conv = acc2[2] <= tgt2;
                 }
             } else {

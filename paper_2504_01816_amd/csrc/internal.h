@@ -157,6 +157,8 @@ struct CocgLaunch {
     double* rhi;           // mixed: nsys x N_d complex float64 residual (starts at the RHS)
     int* refinements;      // mixed: nsys (may be null)
     double refine_tol;     // mixed: residual drop that triggers a reliable update
+    int refine_gap;        // mixed: fewest iterations between reliable updates
+    const float* vloc32;   // mixed: V_loc in float32 for the complex64 sweeps (or null)
     double* b2;            // per system |b|^2: written by the mixed kernel, read by an
                            // FP64 continuation (x_accum) as its tolerance reference; or null
     bool x_accum;          // FP64 continuation: x is added to (not started at 0), and r
@@ -208,5 +210,7 @@ hipError_t launch_grad_accum_d(int64_t nd, int ns, int nvec, const double* psi,
 hipError_t launch_scale(int64_t n, double a, double* x, hipStream_t s);
 hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t s);
 hipError_t launch_fill(int64_t n, double v, double* x, hipStream_t s);
+// dst[i] = float(src[i])
+hipError_t launch_to_float(int64_t n, const double* src, float* dst, hipStream_t s);
 
 }  // namespace rpa

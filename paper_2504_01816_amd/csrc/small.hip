@@ -609,6 +609,18 @@ hipError_t launch_fill(int64_t n, double v, double* x, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void to_float_kernel(int64_t n, const double* __restrict__ src,
+                                float* __restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = float(src[i]);
+}
+
+hipError_t launch_to_float(int64_t n, const double* src, float* dst, hipStream_t s) {
+    hipLaunchKernelGGL(to_float_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, src,
+                       dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(int64_t n, const double* src, double* dst, hipStream_t s) {
     hipLaunchKernelGGL(copy_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, src, dst);
     return hipGetLastError();

@@ -29,7 +29,7 @@ class RpaOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("cocg_max_iter", c_int32), ("cocg_tol", c_double),
                 ("subspace_iters", c_int32), ("freq_mode", c_int32), ("ec_tol", c_double),
                 ("refine_tol", c_double), ("max_systems", c_int32), ("flags", c_int32),
-                ("sq_order", c_int32), ("cocg_block", c_int32)]
+                ("sq_order", c_int32), ("cocg_block", c_int32), ("mixed_min_omega", c_double)]
 
 
 class RpaStats(ctypes.Structure):

@@ -8,6 +8,10 @@ Subcommands (run under rocprofv3, one counter set per run):
              point-iterations and launch count as JSON (stderr)
   summarize  reduce a rocprofv3 counter CSV to per-kernel means (markdown on stdout)
   kstats     a rocprofv3 --stats kernel summary as a markdown table
+  gaps       kernel time and idle time between dispatches of a traced subspace run (what a HIP
+             graph of the small launches could save)
+  krange     mean duration of a range of one kernel's dispatches in a kernel trace (a bench
+             run's timed region)
   traffic    combine the FETCH_SIZE and WRITE_SIZE summaries of the copy and the apply runs
              into HBM bytes per point-iteration of the COCG kernel (JSON read by bench.py)
 
@@ -166,6 +170,61 @@ def cmd_stages(args):
         print("| %s | `%s` | %d | %.3f | | | |" % (label, key, sum(len(dur[k]) for k in ks), t * 1e3))
 
 
+def cmd_gaps(args):
+    """Launch overhead of a traced `subspace` run: per dispatch the kernel time and the idle
+    time since the previous kernel ended, summed for the COCG kernel and for everything else
+    (the ~30 small launches of a subspace iteration around it).  The idle time outside the COCG
+    kernel bounds what capturing those launches in a HIP graph could save."""
+    fn = args.trace
+    if os.path.isdir(fn):
+        fn = sorted(glob.glob(os.path.join(fn, "**", "*kernel_trace.csv"), recursive=True))[0]
+    rows = sorted(csv.DictReader(open(fn)), key=lambda r: int(r["Start_Timestamp"]))
+    if args.skip:
+        rows = rows[args.skip:]
+    k_cocg = k_other = gap_other = 0.0
+    n_other = 0
+    prev_end = None
+    for r in rows:
+        a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        d = (b - a) * 1e-6
+        gap = max(0.0, (a - prev_end) * 1e-6) if prev_end is not None else 0.0
+        if "cocg_wg" in r["Kernel_Name"]:
+            k_cocg += d
+        else:
+            k_other += d
+            gap_other += gap
+            n_other += 1
+        prev_end = b if prev_end is None else max(prev_end, b)
+    span = (int(rows[-1]["End_Timestamp"]) - int(rows[0]["Start_Timestamp"])) * 1e-6
+    print("| quantity | ms |")
+    print("|---|---|")
+    print("| span of the traced dispatches | %.3f |" % span)
+    print("| COCG kernel time | %.3f |" % k_cocg)
+    print("| other kernels (%d dispatches) | %.3f |" % (n_other, k_other))
+    print("| idle time before the other kernels (launch gaps and host synchronisations) | %.3f |"
+          % gap_other)
+    print("| idle share of the span | %.2f%% |" % (100.0 * gap_other / span))
+
+
+def cmd_krange(args):
+    """Mean duration of one kernel's dispatches number a .. b-1 (in dispatch order) in a kernel
+    trace: the dispatches of a bench run's timed region (bench.py prints their range), to set
+    beside the bench's own HIP-event timing of the same launches."""
+    fn = args.trace
+    if os.path.isdir(fn):
+        fn = sorted(glob.glob(os.path.join(fn, "**", "*kernel_trace.csv"), recursive=True))[0]
+    rows = sorted((r for r in csv.DictReader(open(fn)) if args.match in r["Kernel_Name"]),
+                  key=lambda r: int(r["Start_Timestamp"]))
+    sel = rows[args.first:args.last]
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in sel]
+    names = sorted(set(r["Kernel_Name"] for r in sel))
+    print("| kernel | dispatches in the trace | selected | mean ms | min ms | max ms |")
+    print("|---|---|---|---|---|---|")
+    print("| `%s` | %d | %d .. %d | %.3f | %.3f | %.3f |" % (
+        short(names[0] if names else args.match, 90), len(rows), args.first, args.last - 1,
+        sum(d) / max(1, len(d)), min(d) if d else 0.0, max(d) if d else 0.0))
+
+
 def read_counters(path):
     """Rows of a rocprofv3 counter_collection CSV as (kernel, counter, value) per dispatch."""
     rows = []
@@ -289,6 +348,14 @@ def main():
     st = sub.add_parser("stages")
     st.add_argument("trace")
     st.add_argument("--run", required=True, help="JSON written by `subspace --out`")
+    kr = sub.add_parser("krange")
+    kr.add_argument("trace")
+    kr.add_argument("--match", required=True, help="substring of the kernel name")
+    kr.add_argument("--first", type=int, required=True)
+    kr.add_argument("--last", type=int, required=True)
+    gp = sub.add_parser("gaps")
+    gp.add_argument("trace")
+    gp.add_argument("--skip", type=int, default=0, help="leading dispatches to drop (set-up)")
     s = sub.add_parser("summarize")
     s.add_argument("csv")
     s.add_argument("--match", default="")
@@ -307,7 +374,8 @@ def main():
     t.add_argument("--write", default="")
     args = ap.parse_args()
     {"copy": cmd_copy, "apply": cmd_apply, "subspace": cmd_subspace, "stages": cmd_stages,
-     "summarize": cmd_summarize, "kstats": cmd_kstats, "traffic": cmd_traffic}[args.cmd](args)
+     "summarize": cmd_summarize, "kstats": cmd_kstats, "traffic": cmd_traffic,
+     "gaps": cmd_gaps, "krange": cmd_krange}[args.cmd](args)
 
 
 if __name__ == "__main__":

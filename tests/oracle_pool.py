@@ -62,13 +62,16 @@ def _orbital_systems(args):
     return out, it, st
 
 
-def chi0_column(ex, u, vloc, psi, eps, om, shape, h, tol, max_iter):
+def chi0_column(ex, u, vloc, psi, eps, om, shape, h, tol, max_iter, orbitals=None):
     """chi0 applied to one trial vector u, its N_s Sternheimer systems spread over the pool
     (orbitals dealt round-robin, so the hardest ones, next to the gap, land on different
-    workers).  Returns (chi0 u, iterations per orbital, status per orbital)."""
+    workers); with `orbitals`, only those orbitals' terms 4 psi_n Re x_n (the column is the
+    sum of the terms of all orbitals).  Returns (chi0 u or the partial sum, iterations per
+    orbital, status per orbital; zero for orbitals not solved)."""
     ns = psi.shape[1]
-    k = min(ns, n_workers())
-    groups = [list(range(w, ns, k)) for w in range(k)]
+    orbs = list(range(ns)) if orbitals is None else list(orbitals)
+    k = min(len(orbs), n_workers())
+    groups = [orbs[w::k] for w in range(k)]
     jobs = [(u, vloc, psi, eps, om, shape, h, tol, max_iter, g) for g in groups]
     out = np.zeros(u.shape[0])
     it = np.zeros(ns, dtype=np.int64)

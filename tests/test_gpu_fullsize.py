@@ -51,8 +51,9 @@ def test_chi0_full_block_24_sampled_columns(wl1, block1, precision, m):
     dc, U = block1
     om = float(wl1.omegas[m])
     say("24^3 chi0 block of 64 at omega %.4g precision %d" % (om, precision))
+    # mixed_min_omega = 0: the complex64 kernel also at the lowest frequency
     out, rc, st = api.rpa_apply_chi0(dc, om, U, dict(cocg_tol=1e-11, precision=precision,
-                                                     cocg_max_iter=20000))
+                                                     cocg_max_iter=20000, mixed_min_omega=0.0))
     assert rc == 0 and st["cocg_launches"] == 1 and st["cocg_systems"] == 64 * 16
     pick = [0, 41]
     Un = U.cpu().numpy()
@@ -155,42 +156,69 @@ def test_chi0_full_block_48_sampled_column():
         torch.cuda.empty_cache()
 
 
-@pytest.mark.slow
-def test_chi0_full_block_48_low_frequency_column_both_precisions():
-    # the 48^3 block of 256 trial vectors at its second-lowest GL8 frequency (omega = 0.113, a
-    # hard end of the spectrum whose oracle column still finishes in about a minute on the
-    # host cores; at 0.0203 it takes twice that), in the bench's launch configuration: the
-    # row-slab kernel's long solves in FP64 and in the mixed path, where an iteration cap of
-    # 400 makes the hardest complex64 systems stop and finish by the FP64 continuation from
-    # x_hi and the exact residual; tol 1e-10 on every side, compared at 1e-6 (cond(A) tol)
+# The 48^3 block of 256 trial vectors at its second-lowest GL8 frequency (omega = 0.113, a hard
+# end of the spectrum whose oracle column finishes in about a minute on the host cores; at
+# 0.0203 it takes twice that), in the bench's launch configuration: the row-slab kernel's long
+# solves in FP64 and in the mixed path, where an iteration cap of 800 (FP64 needs at most 738
+# here) makes the hardest complex64 systems stop and finish by the FP64 continuation from x_hi
+# and the exact residual; tol 1e-10 on every side, compared at 1e-6 (cond(A) tol).  The
+# oracle's column is the sum of its orbitals' terms 4 psi_n Re x_n, computed in four groups of
+# 16 orbitals (one test each, every group spread over the host cores).
+W48_M, W48_J, W48_TOL = 6, 77, 1e-10
+
+
+@pytest.fixture(scope="module")
+def w48():
     say("generating the 48^3 workload")
     wl = synth.workload(2, device=DEV)
-    c = wl.cells[0]
-    dc = api.device_cell(c, DEV)
+    dc = api.device_cell(wl.cells[0], DEV)
     U = api.rpa_apply_coulomb(dc, torch.tensor(wl.V0[0], device=DEV), 1)
-    m, j, tol = 6, 77, 1e-10
-    om = float(wl.omegas[m])
-    u = U[j].cpu().numpy()
-    got = {}
-    for precision, cap in ((0, 20000), (MIXED, 400)):
+    return dict(wl=wl, dc=dc, U=U, got={}, parts={})
+
+
+@pytest.mark.slow
+def test_chi0_full_block_48_low_frequency_both_precisions(w48):
+    om = float(w48["wl"].omegas[W48_M])
+    for precision, cap in ((0, 20000), (MIXED, 800)):
         say("48^3 chi0 block of 256 at omega %.4g precision %d cap %d" % (om, precision, cap))
-        out, rc, st = api.rpa_apply_chi0(dc, om, U, dict(cocg_tol=tol, precision=precision,
-                                                         cocg_max_iter=cap))
+        out, rc, st = api.rpa_apply_chi0(w48["dc"], om, w48["U"],
+                                         dict(cocg_tol=W48_TOL, precision=precision,
+                                              cocg_max_iter=cap))
         say("status %d, iterations %d (max %d), FP64 continuations %d" % (
             rc, st["cocg_iters_total"], st["cocg_iters_max"], st["fp64_fallbacks"]))
         assert rc == 0 and st["cocg_systems"] == 256 * 64 and st["n_unconverged"] == 0
         if precision == MIXED:
             assert st["fp64_fallbacks"] > 0
-        got[precision] = out[j].cpu().numpy()
+        w48["got"][precision] = out[W48_J].cpu().numpy()
         del out
         torch.cuda.empty_cache()
-    say("oracle column %d at 48^3 (%d workers)" % (j, oracle_pool.n_workers()))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("group", range(4))
+def test_chi0_full_block_48_low_frequency_oracle_part(w48, group):
+    wl = w48["wl"]
+    c = wl.cells[0]
+    psi = np.ascontiguousarray(c.psi.T)
+    orbs = list(range(16 * group, 16 * group + 16))
+    say("oracle orbitals %d-%d of column %d at 48^3 (%d workers)" % (
+        orbs[0], orbs[-1], W48_J, oracle_pool.n_workers()))
+    u = w48["U"][W48_J].cpu().numpy()
     with oracle_pool.pool() as ex:
-        ref, it, st = oracle_pool.chi0_column(ex, u, c.vloc, np.ascontiguousarray(c.psi.T),
-                                              c.eps, om, c.shape, c.h, tol, 20000)
-    say("oracle iterations per orbital: max %d, total %d" % (it.max(), it.sum()))
-    assert np.all(st == 0)
-    for precision, v in got.items():
+        part, it, st = oracle_pool.chi0_column(ex, u, c.vloc, psi, c.eps,
+                                               float(wl.omegas[W48_M]), c.shape, c.h, W48_TOL,
+                                               20000, orbitals=orbs)
+    say("iterations: max %d, total %d" % (it[orbs].max(), it[orbs].sum()))
+    assert np.all(st[orbs] == 0)
+    w48["parts"][group] = part
+
+
+@pytest.mark.slow
+def test_chi0_full_block_48_low_frequency_matches_oracle(w48):
+    if len(w48["parts"]) < 4 or len(w48["got"]) < 2:
+        pytest.skip("needs the GPU columns and the four oracle parts of this module")
+    ref = sum(w48["parts"][g] for g in range(4))
+    for precision, v in w48["got"].items():
         say("precision %d: relative difference %.3e" % (precision, rel(v, ref)))
         assert rel(v, ref) < 1e-6
 

@@ -28,37 +28,72 @@ def frozen_energy(dc, vloc, om, W, Vm, tol):
     return r["E"]
 
 
-@pytest.mark.slow
-def test_gradient_matches_finite_differences_32():
-    # the 32^3 gradient workload: 20 seeded grid points, step 1e-4 Ha, every frequency of the
-    # GL8 rule (the gradient is the sum of the eight per-frequency terms)
+@pytest.fixture(scope="module")
+def wl4():
+    say("generating the 32^3 gradient workload")
     wl = synth.workload(4, device=DEV)
-    c = wl.cells[0]
-    dc = api.device_cell(c, DEV)
-    pick = list(range(len(wl.omegas)))
-    om, W = wl.omegas[pick], wl.weights[pick]
-    tol = 1e-12
-    say("32^3 forward (3 subspace iterations at %d frequencies)" % len(pick))
-    res = api.rpa_energy(dc, 128, om, W, [torch.tensor(wl.V0[0], device=DEV)],
-                         dict(cocg_tol=tol, subspace_iters=3, ec_tol=0.0), save=True)
-    assert res["status"] == 0
-    grad, rc, _ = api.rpa_energy_backward(dc, om, W, res["Vsave"][0], res["Csave"][0], 1.0,
-                                          dict(cocg_tol=tol))
-    assert rc == 0
-    g = grad.cpu().numpy()
-    pts, dlt = wl.extra["fd_points"], wl.extra["fd_step"]
-    fd = np.zeros(len(pts))
-    for i, p in enumerate(pts):
-        e = []
-        for sgn in (1.0, -1.0):
-            v = dc.vloc.clone()
-            v[int(p)] += sgn * dlt
-            e.append(sum(frozen_energy(dc, v, om[m], W[m], res["Vsave"][0][m], tol)
-                         for m in range(len(pick))))
-        fd[i] = (e[0] - e[1]) / (2 * dlt)
-        say("point %d: adjoint %.10e  fd %.10e" % (p, g[p], fd[i]))
-    err = np.abs(g[pts] - fd).max() / np.abs(fd).max()
-    say("max relative difference %.3e" % err)
+    return wl, api.device_cell(wl.cells[0], DEV)
+
+
+@pytest.fixture(scope="module")
+def fd_terms(wl4):
+    """Per frequency m (computed on first use, kept for the module): the adjoint term of
+    dE_c/dV_loc at the 20 seeded points and its central difference (step 1e-4 Ha) of that
+    frequency's frozen-subspace energy."""
+    wl, dc = wl4
+    done = {}
+
+    def term(m):
+        if m in done:
+            return done[m]
+        om, W = wl.omegas[[m]], wl.weights[[m]]
+        tol = 1e-12
+        say("32^3 forward (3 subspace iterations) at omega %.4g" % om[0])
+        res = api.rpa_energy(dc, 128, om, W, [torch.tensor(wl.V0[0], device=DEV)],
+                             dict(cocg_tol=tol, subspace_iters=3, ec_tol=0.0), save=True)
+        assert res["status"] == 0
+        grad, rc, _ = api.rpa_energy_backward(dc, om, W, res["Vsave"][0], res["Csave"][0], 1.0,
+                                              dict(cocg_tol=tol))
+        assert rc == 0
+        pts, dlt = wl.extra["fd_points"], wl.extra["fd_step"]
+        g = grad.cpu().numpy()[pts]
+        fd = np.zeros(len(pts))
+        for i, p in enumerate(pts):
+            e = []
+            for sgn in (1.0, -1.0):
+                v = dc.vloc.clone()
+                v[int(p)] += sgn * dlt
+                e.append(frozen_energy(dc, v, om[0], W[0], res["Vsave"][0][0], tol))
+            fd[i] = (e[0] - e[1]) / (2 * dlt)
+        done[m] = (g, fd)
+        return done[m]
+
+    return term
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("m", range(8))
+def test_gradient_term_matches_finite_differences_32(fd_terms, m):
+    # each frequency's term against the central difference of its frozen-subspace energy: to
+    # 1e-5 of the term's largest value, above the difference quotient's noise floor (energies
+    # solved to tol 1e-12 carry a few 1e-13 Ha of solver noise, over a step of 2e-4 Ha: a few
+    # 1e-9); at the highest frequency the term itself is below 1e-7 and the floor decides
+    g, fd = fd_terms(m)
+    for gi, fi in zip(g, fd):
+        say("adjoint %.10e  fd %.10e" % (gi, fi))
+    err = np.abs(g - fd).max()
+    say("term %d: max difference %.3e, largest value %.3e" % (m, err, np.abs(fd).max()))
+    assert err <= 1e-5 * np.abs(fd).max() + 3e-9
+
+
+@pytest.mark.slow
+def test_gradient_matches_finite_differences_32(fd_terms):
+    # dE_c/dV_loc over the whole GL8 rule (the sum of the eight terms) against the central
+    # difference of the frozen-subspace E_c at the 20 seeded points: 1e-5 relative
+    g = sum(fd_terms(m)[0] for m in range(8))
+    fd = sum(fd_terms(m)[1] for m in range(8))
+    err = np.abs(g - fd).max() / np.abs(fd).max()
+    say("E_c gradient over 8 frequencies: max relative difference %.3e" % err)
     assert err < 1e-5
 
 
