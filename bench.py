@@ -309,7 +309,7 @@ def run_cycle(args):
                      "traffic_bytes_per_point_iter": tb,
                      "traffic_GBs": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
                      "alg_bytes_per_point_iter": alg_pp,
-                     "cocg_share_of_step": cocg_ms * 1e-3 / T,
+                     "cocg_share_of_step": sum(s["cocg_kernel_ms"] for s in steps) * 1e-3 / T,
                      "timing": "HIP events on the launch stream"},
     }
     # time-to-E_c: rpa_energy from V0 at a fixed subspace count per frequency, every frequency

@@ -75,6 +75,10 @@ def cmd_apply(args):
     prec = L.RPA_FP64 if args.precision == "fp64" else L.RPA_MIXED
     opts = dict(precision=prec, cocg_tol=wl.cocg_tol, flags=L.RPA_FLAG_PRECOND if args.precond else 0,
                 cocg_block=args.block)
+    if args.refine_tol > 0:
+        opts["refine_tol"] = args.refine_tol
+    if args.mixed_min_omega >= 0:
+        opts["mixed_min_omega"] = args.mixed_min_omega
     tot = {"cocg_point_iters": 0.0, "cocg_launches": 0, "cocg_kernel_ms": 0.0, "cocg_iters_total": 0}
     idx = range(len(wl.omegas)) if args.omega_index < 0 else [args.omega_index]
     if args.warmup:
@@ -336,6 +340,11 @@ def main():
                    help="preconditioned COCG (Kronecker shifted-Laplacian preconditioner)")
     a.add_argument("--block", type=int, default=0,
                    help="block COCG width (options.cocg_block; 0: single systems)")
+    a.add_argument("--refine-tol", type=float, default=0.0,
+                   help="mixed: refine_tol (0: the library default)")
+    a.add_argument("--mixed-min-omega", type=float, default=-1.0,
+                   help="mixed: options.mixed_min_omega (negative: the library default; 0: "
+                        "complex64 at every frequency)")
     a.add_argument("--box", action="store_true",
                    help="an isolated (Dirichlet) box of the workload's grid instead of its cell")
     ss = sub.add_parser("subspace")
