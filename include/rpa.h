@@ -197,6 +197,24 @@ int rpa_apply_coulomb(const rpa_cell* cell, int32_t power, int32_t nvec, const d
                       double* out, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * rpa_apply_coulomb without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same operation, arguments and results as rpa_apply_coulomb.  Its scratch space (the 1D
+ * bases and the transform buffer) is a static 32 MiB device array inside the library: every
+ * GPU the library runs on holds its own copy from the first call on that device until the
+ * process ends.  The call allocates nothing and enqueues its work on `stream`; the vectors
+ * are transformed in passes of as many columns as the scratch holds (one column needs about
+ * 8 N_d bytes).  Every call on one GPU shares that GPU's array and leaves its contents there:
+ * calls that overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.
+ *   in, out  device, N_d x nvec column-major float64 (out may equal in)
+ * Returns RPA_EWORKSPACE (with a message naming the sizes) when one column of the grid and
+ * its bases exceed the 32 MiB scratch (from about 4 million grid points).
+ */
+int rpa_apply_coulomb_noalloc(const rpa_cell* cell, int32_t power, int32_t nvec, const double* in,
+                              double* out, void* stream);
+
+/*
  * out = chi0(i omega) in, one "chi0 block-apply" (Eqs. 7-9, Algorithm 1 inner loops):
  * for every orbital n and column u_j of `in`, b = psi_n .* u_j, c = h^3 Psi^T b,
  * b' = b - Psi c, COCG on (H - eps_n - i omega) x = -b' from x = 0 to

@@ -112,6 +112,19 @@ def rpa_apply_coulomb(cell, X, power=1, out=None):
     return out
 
 
+def rpa_apply_coulomb_noalloc(cell, X, power=1, out=None):
+    """nu^{power/2} X through the allocation-free entry point (the library's static device
+    scratch, no workspace); out must be preallocated by the caller when given."""
+    _check_block(X, cell.nd, "X")
+    k = X.shape[0]
+    out = torch.empty_like(X) if out is None else out
+    c = cell.c_struct()
+    _L.check(_L.load().rpa_apply_coulomb_noalloc(ctypes.byref(c), power, k, X.data_ptr(),
+                                                 out.data_ptr(), _stream()),
+             "rpa_apply_coulomb_noalloc")
+    return out
+
+
 def rpa_apply_chi0(cell, omega, X, opts=None):
     """chi0(i omega) X by DFPT/COCG; returns (out, status, stats dict)."""
     _check_block(X, cell.nd, "X")

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librpa_gfx950.so")
 SOURCES = ["api.hip", "cocg.hip", "cocg_f64.hip", "cocg_mixed.hip", "gemm.hip", "small.hip",
-           "pcocg.hip"]
+           "pcocg.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

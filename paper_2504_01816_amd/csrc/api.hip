@@ -1340,6 +1340,44 @@ int rpa_apply_coulomb(const rpa_cell* cell, int32_t power, int32_t nvec, const d
     return RPA_OK;
 }
 
+int rpa_apply_coulomb_noalloc(const rpa_cell* cell, int32_t power, int32_t nvec,
+                              const double* in, double* out, void* stream) {
+    g_last_error.clear();
+    RPA_CHECK(check_geometry(cell));
+    if (power != 1 && power != 2) return fail(RPA_EINVAL, "power must be 1 or 2");
+    if (nvec < 1 || nvec > 65535) return fail(RPA_EINVAL, "nvec must be in [1, 65535]");
+    if (!in || !out) return fail(RPA_EINVAL, "in/out pointer is NULL");
+    const Grid g = grid_of(cell);
+    const size_t cap = noalloc_scratch_bytes();
+    // the 1D bases and one vector's transform buffer must fit; then as many vectors per pass
+    // as the scratch holds
+    auto need = [&](int k) {
+        Carver dry;
+        CoulombBuf b;
+        carve_coulomb(dry, g, k, b);
+        return dry.used;
+    };
+    if (need(1) > cap)
+        return fail(RPA_EWORKSPACE, "grid too large for the static scratch: one vector needs " +
+                                        std::to_string(need(1)) + " bytes, the scratch holds " +
+                                        std::to_string(cap));
+    int chunk = int(std::min<int64_t>(nvec, int64_t((cap - need(1)) / (8 * size_t(g.nd()))) + 1));
+    while (chunk > 1 && need(chunk) > cap) --chunk;
+    void* base = nullptr;
+    RPA_CHECK(noalloc_scratch(&base));
+    Carver cv{static_cast<char*>(base), 0};
+    CoulombBuf b;
+    carve_coulomb(cv, g, chunk, b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RPA_CHECK(coulomb_setup(g, b, s));
+    const int64_t nd = g.nd();
+    for (int j0 = 0; j0 < nvec; j0 += chunk) {
+        const int nv = std::min(chunk, nvec - j0);
+        RPA_CHECK(coulomb_apply(g, b, power, nv, in + nd * j0, out + nd * j0, s));
+    }
+    return RPA_OK;
+}
+
 int rpa_apply_chi0(const rpa_cell* cell, double omega, int32_t nvec, const double* in,
                    double* out, const rpa_options* opt, rpa_stats* stats, void* ws,
                    size_t ws_bytes, void* stream) {

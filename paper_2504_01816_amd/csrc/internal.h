@@ -170,6 +170,11 @@ hipError_t launch_cocg(const CocgLaunch& a, hipStream_t s);
 // with one column per thread), in FP64 and, with `mixed`, also in complex64.  No device call.
 bool cocg_shape_exists(const Grid& g, bool mixed);
 
+// Static device scratch of the allocation-free entry point (noalloc.hip): its size, and its
+// device address on the current device (looked up once per device with hipGetSymbolAddress).
+size_t noalloc_scratch_bytes();
+int noalloc_scratch(void** out);
+
 // Delta rho epilogue: out[r, j] = 4 sum_n psi[r,n] Re x[n + ns*j][r]; x is float64 with
 // `stride` doubles per point (1: real parts only, 2: complex interleaved)
 hipError_t launch_drho(int64_t nd, int ns, int nvec, const double* psi, const double* x,

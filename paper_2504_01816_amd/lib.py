@@ -57,6 +57,8 @@ _SIGS = {
                                      c_int32, POINTER(RpaOptions), POINTER(c_size_t)]),
     "rpa_apply_coulomb": (c_int32, [POINTER(RpaCell), c_int32, c_int32, c_void_p, c_void_p,
                                     c_void_p, c_size_t, c_void_p]),
+    "rpa_apply_coulomb_noalloc": (c_int32, [POINTER(RpaCell), c_int32, c_int32, c_void_p,
+                                            c_void_p, c_void_p]),
     "rpa_apply_chi0": (c_int32, [POINTER(RpaCell), c_double, c_int32, c_void_p, c_void_p,
                                  POINTER(RpaOptions), POINTER(RpaStats), c_void_p, c_size_t,
                                  c_void_p]),
