@@ -460,7 +460,8 @@ def run_energy(args):
         # the COCG time; the forward wall time bounds it from above instead
         fwd = sum(s["fwd_s"] for s in steps)
         achieved = alg / fwd / 1e9
-        timing = "forward wall time (concurrent cells)"
+        timing = ("forward wall time (cells one after another)" if args.cells_sequential
+                  else "forward wall time (concurrent cells)")
     traffic, tb = cocg_traffic(wl.name, args.precision, pit / max(1, launches))
     kernel = "cocg_wg (batched COCG, one workgroup per system)"
     if args.precond or args.block >= 2:

@@ -137,7 +137,7 @@ typedef struct rpa_options {
                                 solved in FP64 (complex128 state) instead of complex64: near the
                                 real axis the shifts approach the spectrum and the complex64
                                 recurrences need more extra iterations than they save; 0 runs
-                                every frequency in complex64.  Default 0.05. */
+                                every frequency in complex64.  Default 0.2. */
 } rpa_options;
 
 /* Counters accumulated by a call (added to the struct's current contents). */

@@ -47,9 +47,12 @@ constexpr int kVersion = 10100;
 
 // RPA_MIXED: frequencies below this (Ha) solve in FP64.  Near the real axis the Sternheimer
 // shifts come close to the spectrum and the complex64 recurrences lose conjugacy: measured on
-// the 48^3 cell, complex64 needs 2.2x the FP64 iterations at omega = 0.0203 (up to 5x for the
-// orbitals next to the gap), more than its per-iteration saving.
-constexpr double kMixedMinOmega = 0.05;
+// the 48^3 cell, complex64 needs 1.28x the FP64 iterations at omega = 0.311, 1.55x at 0.113
+// and 2.2x at 0.0203 (up to 5x for the orbitals next to the gap), against a per-iteration
+// saving of 1.45-1.6x; per block-apply the two tie at 0.311 and FP64 is 1.3x faster at 0.113
+// (on the 24^3 cell, where the kernel saves less per iteration, FP64 is already 1.16x faster
+// at 0.311).  The 8-point rule has no node between 0.113 and 0.311.
+constexpr double kMixedMinOmega = 0.2;
 
 // RPA_MIXED: default relative drop of the complex64 residual that triggers a reliable update.
 // Measured on the 48^3 cell (complex64 at every frequency): 0.3 takes 3-10% less time than 0.1
@@ -615,7 +618,8 @@ bool fp64_in_mixed(const Chi0Buf& b, const Opts& o, double w) {
 // points at column j0), each at its own frequency h.omega[j].  With mixed buffers and
 // fp64_run, the run solves in FP64 inside the mixed state: the complex128 residual goes in
 // r_hi, the two complex128 direction vectors in [r | p_a] and [p_b | x_lo] (as for the
-// continuation of capped systems), the complex solution in x_hi.
+// continuation of capped systems), the solution in the x_hi buffer: complex if x_complex,
+// else only its real part, packed as in the FP64 path (what Delta rho reads).
 int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Buf& b,
                 const double* U, int64_t j0, int nv, bool x_complex, Chi0Host& h,
                 hipStream_t s, bool fp64_run = false) {
@@ -722,7 +726,7 @@ int solve_chunk(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Bu
         L.r = b.rhi;
         L.pa = b.r;
         L.pb = b.pb;
-        L.x_complex = true;
+        L.x_complex = x_complex;
         L.fp32 = false;
         L.refinements = b.refine;      // written as 0 by the FP64 kernel
         hipEvent_t e0, e1;
@@ -846,8 +850,9 @@ int chi0_apply(const rpa_cell* cell, const Grid& g, int nvec, const double* in, 
         RPA_CHECK(solve_chunk(cell, g, o, b, in + nd * j0, j0, nv, false, h, s, f64));
         RPA_CHECK(tally(b, ns * nv, nd, t, h, int64_t(j0) * ns, s));
         if (!f64) RPA_CHECK(continue_capped(cell, g, o, b, nv, h, t, s));
+        // an FP64 run in mixed buffers leaves the real part packed (solve_chunk)
         RPA_HIP(launch_drho(nd, ns, nv, cell->psi, reinterpret_cast<const double*>(b.x),
-                            b.x_complex ? 2 : 1, out + nd * j0, s));
+                            (b.x_complex && !f64) ? 2 : 1, out + nd * j0, s));
         j0 += nv;
     }
     return RPA_OK;

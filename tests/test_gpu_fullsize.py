@@ -181,9 +181,10 @@ def test_chi0_full_block_48_low_frequency_both_precisions(w48):
     om = float(w48["wl"].omegas[W48_M])
     for precision, cap in ((0, 20000), (MIXED, 800)):
         say("48^3 chi0 block of 256 at omega %.4g precision %d cap %d" % (om, precision, cap))
+        # mixed_min_omega = 0: complex64 at this frequency (the default solves it in FP64)
         out, rc, st = api.rpa_apply_chi0(w48["dc"], om, w48["U"],
                                          dict(cocg_tol=W48_TOL, precision=precision,
-                                              cocg_max_iter=cap))
+                                              cocg_max_iter=cap, mixed_min_omega=0.0))
         say("status %d, iterations %d (max %d), FP64 continuations %d" % (
             rc, st["cocg_iters_total"], st["cocg_iters_max"], st["fp64_fallbacks"]))
         assert rc == 0 and st["cocg_systems"] == 256 * 64 and st["n_unconverged"] == 0

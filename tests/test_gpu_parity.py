@@ -163,7 +163,9 @@ def test_backward_matches_oracle_adjoint():
     say("rpa_energy_backward 12^3 N_s=3 N_r=6 two frequencies")
     c = synth.small_cell(n=12, h=0.5, n_wells=2, n_occ=3, seed=11)
     dc = api.device_cell(c, DEV)
-    om, W = np.array([2.0, 0.7]), np.array([0.6, 0.9])
+    # 0.1 lies below the default mixed_min_omega: that frequency's solves run the FP64 kernel
+    # inside the mixed buffers, with complex solutions for the gradient epilogue
+    om, W = np.array([2.0, 0.1]), np.array([0.6, 0.9])
     V0 = np.random.default_rng(6).standard_normal((6, c.nd))
     opts = dict(cocg_tol=1e-12, subspace_iters=3, ec_tol=0.0)
     res = api.rpa_energy(dc, 6, om, W, [torch.tensor(V0, device=DEV)], opts, save=True)
@@ -206,20 +208,24 @@ def test_mixed_chi0_extreme_frequencies(wl0, dc0, omega):
 
 
 def test_mixed_path_solves_low_frequencies_in_fp64(wl0, dc0):
-    # below options.mixed_min_omega (default 0.05) the mixed path runs the FP64 kernel on its
+    # below options.mixed_min_omega (default 0.2) the mixed path runs the FP64 kernel on its
     # own buffers: the same recurrence as the FP64 path, so the same chi0 bit for bit, and no
     # complex64 refinements; above it, complex64 with refinements
     c = wl0.cells[0]
-    say("mixed path: FP64 below mixed_min_omega")
+    thr = L.default_options().mixed_min_omega
+    say("mixed path: FP64 below mixed_min_omega", thr)
     U = torch.tensor(np.random.default_rng(4).standard_normal((4, c.nd)), device=DEV)
     o = dict(cocg_tol=1e-10)
-    for omega in (0.02, 0.049):
+    for omega in (0.02, 0.98 * thr):
         mx, rc, st = api.rpa_apply_chi0(dc0, omega, U, dict(o, precision=MIXED))
         f64, rc2, st2 = api.rpa_apply_chi0(dc0, omega, U, o)
         assert rc == 0 and rc2 == 0 and st["refinements"] == 0
         assert torch.equal(mx, f64)
         assert st["cocg_iters_total"] == st2["cocg_iters_total"]
-    mx, rc, st = api.rpa_apply_chi0(dc0, 0.05, U, dict(o, precision=MIXED))
+    mx, rc, st = api.rpa_apply_chi0(dc0, thr, U, dict(o, precision=MIXED))
+    assert rc == 0 and st["refinements"] > 0
+    # an explicit threshold moves the boundary
+    mx, rc, st = api.rpa_apply_chi0(dc0, 0.05, U, dict(o, precision=MIXED, mixed_min_omega=0.05))
     assert rc == 0 and st["refinements"] > 0
     # a block whose vectors straddle the threshold (batched frequencies) splits into launches
     om, W = np.array([1.0, 0.03]), np.array([1.0, 1.0])
@@ -247,7 +253,9 @@ def test_mixed_backward_matches_fp64():
     say("mixed backward vs fp64 backward 12^3")
     c = synth.small_cell(n=12, h=0.5, n_wells=2, n_occ=3, seed=11)
     dc = api.device_cell(c, DEV)
-    om, W = np.array([2.0, 0.7]), np.array([0.6, 0.9])
+    # 0.1 lies below the default mixed_min_omega: that frequency's solves run the FP64 kernel
+    # inside the mixed buffers, with complex solutions for the gradient epilogue
+    om, W = np.array([2.0, 0.1]), np.array([0.6, 0.9])
     V0 = np.random.default_rng(6).standard_normal((6, c.nd))
     o64 = dict(cocg_tol=1e-11, subspace_iters=3, ec_tol=0.0)
     res = api.rpa_energy(dc, 6, om, W, [torch.tensor(V0, device=DEV)], o64, save=True)

@@ -106,10 +106,12 @@ def test_slab_mixed_capped_systems_continue_in_fp64(periodic, monkeypatch, capfd
     ref, iters, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, 0.05, c.shape, c.h, 1e-10,
                                      5000)
     cap = int(1.25 * iters.max())       # FP64 from scratch fits; the complex64 stage does not
+    # mixed_min_omega = 0: complex64 at this frequency (the default solves it in FP64)
     out, rc, st = api.rpa_apply_chi0(dc, 0.05, torch.tensor(U, device=DEV),
-                                     dict(cocg_tol=1e-10, cocg_max_iter=cap, precision=1))
+                                     dict(cocg_tol=1e-10, cocg_max_iter=cap, precision=1,
+                                          mixed_min_omega=0.0))
     say("cap", cap, "fallbacks", st["fp64_fallbacks"], "unconverged", st["n_unconverged"])
-    assert rc == 0 and st["n_unconverged"] == 0
+    assert rc == 0 and st["n_unconverged"] == 0 and st["fp64_fallbacks"] > 0
     # two solutions meeting tol 1e-10 differ by up to cond(A) tol at this frequency
     assert rel(out.cpu().numpy().T, ref) < 5e-8
     assert "nslab=2" in capfd.readouterr().err
