@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--refine-tol", type=float, default=0.0,
                     help="mixed: relative residual drop between reliable updates (0: library "
                          "default)")
+    ap.add_argument("--mixed-min-omega", type=float, default=-1.0,
+                    help="mixed: frequencies below this (Ha) solve in FP64 (negative: library "
+                         "default)")
     ap.add_argument("--ec-iters", type=int, default=1,
                     help="cycle mode: fixed subspace iterations per frequency of the "
                          "time-to-E_c runs")
@@ -217,6 +220,8 @@ def run_cycle(args):
         o = dict(precision=prec[p], cocg_tol=wl.cocg_tol, subspace_iters=1, ec_tol=0.0)
         if args.refine_tol > 0:
             o["refine_tol"] = args.refine_tol
+        if args.mixed_min_omega >= 0:
+            o["mixed_min_omega"] = args.mixed_min_omega
         return o
 
     def step(k):
@@ -259,7 +264,8 @@ def run_cycle(args):
     # class is priced at its own algorithmic bytes over the steps whose only COCG launch is
     # that kernel (a step with FP64 continuations adds FP64 launches and is left out); the
     # roofline reports the class with the larger share of the timed region's kernel time.
-    min_om = L.default_options().mixed_min_omega if args.precision == "mixed" else 0.0
+    min_om = (args.mixed_min_omega if args.mixed_min_omega >= 0
+              else L.default_options().mixed_min_omega) if args.precision == "mixed" else 0.0
 
     def kclass(s):
         return args.precision if wl.omegas[s["m"]] >= min_om else "fp64"
@@ -316,7 +322,7 @@ def run_cycle(args):
                    "step": "one subspace iteration (one chi0 block-apply of %d vectors) at "
                            "frequency step mod %d" % (nr, nf),
                    "refine_tol": args.refine_tol or L.default_options().refine_tol,
-                   "mixed_min_omega": L.default_options().mixed_min_omega},
+                   "mixed_min_omega": min_om},
         "step_ms_per_frequency": {"%.4g" % wl.omegas[m]: 1e3 * float(np.mean(v))
                                   for m, v in sorted(per_freq.items())},
         "roofline": roof,
@@ -348,6 +354,8 @@ def run_cycle(args):
             flush=True)
         torch.cuda.empty_cache()
     out["time_to_ec_s"] = ec[args.precision]["time_to_ec_s"]
+    out["time_to_ec_label"] = ("fixed count of %d subspace iteration(s) per frequency, every "
+                               "frequency from V0 (no energy test)" % args.ec_iters)
     out["E_c"] = ec[args.precision]["E_c"]
     out["time_to_ec_runs"] = ec
     if len(ec) > 1:
@@ -473,6 +481,25 @@ def run_energy(args):
                   else "forward wall time (concurrent cells)")
     traffic, tb = cocg_traffic(wl.name, args.precision, pit / max(1, launches))
     kernel = "cocg_wg (batched COCG, one workgroup per system)"
+
+    def converged(iters):
+        # per cell and frequency: whether the relative energy test held before the cap (a
+        # fixed subspace count, ec_tol = 0, has no test and reports None)
+        if opts["ec_tol"] <= 0.0:
+            return None
+        cap = opts["subspace_iters"]
+        return [[bool(k < cap) for k in row] for row in iters]
+
+    def ec_label(iters):
+        if opts["ec_tol"] <= 0.0:
+            return "fixed count of %d subspace iterations per frequency" % opts["subspace_iters"]
+        cv = converged(iters)
+        n_cap = sum(1 for row in cv for c in row if not c)
+        if n_cap == 0:
+            return "energy test (ec_tol %g) held at every frequency" % opts["ec_tol"]
+        return ("not converged: %d of %d frequencies stopped at the cap of %d subspace "
+                "iterations before the energy test (ec_tol %g) held" % (
+                    n_cap, sum(len(row) for row in cv), opts["subspace_iters"], opts["ec_tol"]))
     if args.precond or args.block >= 2:
         # the host-driven solvers: a launch is a whole solve of several kernels, and the
         # counters were taken on the plain kernel
@@ -495,9 +522,11 @@ def run_energy(args):
                    "freq_mode": args.freq_mode, "sq_order": args.sq_order,
                    "precond": bool(args.precond), "cocg_block": args.block},
         "time_to_ec_s": float(np.mean([s["fwd_s"] for s in steps])),
+        "time_to_ec_label": ec_label(steps[-1]["iters"]),
         "backward_s": float(np.mean([s["bwd_s"] for s in steps])),
         "E_c": steps[-1]["E"],
         "subspace_iters": steps[-1]["iters"],
+        "converged": converged(steps[-1]["iters"]),
         "chi0_applies_per_step": applies / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -528,7 +557,8 @@ def run_energy(args):
             "precision": other, "precond": False,
             "chi0_block_applies_per_s": s2["applies"] / t,
             "time_to_ec_s": s2["fwd_s"], "backward_s": s2["bwd_s"],
-            "E_c": s2["E"], "subspace_iters": s2["iters"],
+            "E_c": s2["E"], "subspace_iters": s2["iters"], "converged": converged(s2["iters"]),
+            "time_to_ec_label": ec_label(s2["iters"]),
             "E_c_rel_diff": [abs(a - b) / abs(b) for a, b in zip(s2["E"], steps[-1]["E"])],
             "cocg_alg_GBs": ALG_BYTES[other] * s2["point_iters"] / (s2["cocg_ms"] * 1e-3) / 1e9,
             "time_to_ec_ratio_vs_main": s2["fwd_s"] / out["time_to_ec_s"],

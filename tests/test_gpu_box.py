@@ -48,8 +48,10 @@ def test_box_chi0_matches_oracle(box, precision, omega):
     c, dc = box
     say("box chi0 omega", omega, "precision", precision)
     U = np.random.default_rng(2).standard_normal((5, c.nd))
+    # mixed_min_omega = 0: the mixed path runs its complex64 kernel at both frequencies
     out, rc, st = api.rpa_apply_chi0(dc, omega, torch.tensor(U, device=DEV),
-                                     dict(cocg_tol=1e-12, precision=precision))
+                                     dict(cocg_tol=1e-12, precision=precision,
+                                          mixed_min_omega=0.0))
     ref, _, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, omega, c.shape, c.h, 1e-12, 5000,
                                  bc=BOX)
     assert rc == 0 and rel(out.cpu().numpy().T, ref) < 1e-9

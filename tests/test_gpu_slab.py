@@ -50,8 +50,10 @@ def test_slab_chi0_periodic_matches_oracle(periodic, monkeypatch, capfd, shape, 
     forced(monkeypatch, shape)
     U = np.random.default_rng(5).standard_normal((3, c.nd))
     for omega in (1.0, 0.05):
+        # mixed_min_omega = 0: the mixed path runs its complex64 kernel at both frequencies
         out, rc, st = api.rpa_apply_chi0(dc, omega, torch.tensor(U, device=DEV),
-                                         dict(cocg_tol=1e-12, precision=precision))
+                                         dict(cocg_tol=1e-12, precision=precision,
+                                              mixed_min_omega=0.0))
         ref, _, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, omega, c.shape, c.h, 1e-12,
                                      5000)
         assert rc == 0 and st["n_unconverged"] == 0
@@ -68,8 +70,10 @@ def test_slab_chi0_box_matches_oracle(box, monkeypatch, capfd, shape, precision)
     forced(monkeypatch, shape)
     U = np.random.default_rng(6).standard_normal((3, c.nd))
     for omega in (1.0, 0.05):
+        # mixed_min_omega = 0: the mixed path runs its complex64 kernel at both frequencies
         out, rc, st = api.rpa_apply_chi0(dc, omega, torch.tensor(U, device=DEV),
-                                         dict(cocg_tol=1e-12, precision=precision))
+                                         dict(cocg_tol=1e-12, precision=precision,
+                                              mixed_min_omega=0.0))
         ref, _, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, omega, c.shape, c.h, 1e-12,
                                      5000, bc="dirichlet")
         assert rc == 0 and st["n_unconverged"] == 0
