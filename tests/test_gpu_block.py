@@ -4,11 +4,12 @@ against the oracle's block COCG and its plain DFPT, element by element: widths 2
 ragged blocks, chunked launches, an isolated box, a zero column and the iteration cap, equal
 trial vectors (split blocks), the batched-frequency energy with its backward, row-slab steps
 with the GEMM preconditioner passes, the gathered step where no march shape fits, and the
-24^3 cell against the plain solver."""
+24^3 cell against the plain solver and the oracle's plain DFPT."""
 import numpy as np
 import pytest
 import torch
 
+import oracle_pool
 from oracle import chi0 as ochi0
 from oracle import energy as oenergy
 from oracle import gradient as ograd
@@ -188,16 +189,31 @@ def test_block_batched_energy_and_backward_match_oracle():
     assert rc == 0 and rel(grad.cpu().numpy(), gref) < 1e-8
 
 
-@pytest.mark.parametrize("width,pre", [(4, True), (4, False)])
-def test_block_cell24_matches_single_system_solver(width, pre):
-    # the benchmark's 24^3 cell and block of 64 trial vectors (1024 systems, 256 blocks of 4):
-    # block and single-system solves of the same systems give the same chi0 to the solver
-    # tolerance; every block is checked, through the output columns of every vector
+@pytest.fixture(scope="module")
+def cell24_block():
+    # the benchmark's 24^3 cell, a block of 64 trial vectors, and the oracle's plain DFPT chi0
+    # (Eqs. 7-9, its own COCG) of two of them, computed once on the host cores
     wl = synth.workload(1, device=DEV)
     c = wl.cells[0]
     dc = api.device_cell(c, DEV)
+    Un = np.random.default_rng(46).standard_normal((64, c.nd))
+    pick = [5, 46]
+    say("oracle chi0 24^3, vectors", pick)
+    with oracle_pool.pool() as ex:
+        ref, _, _ = oracle_pool.chi0_apply(ex, Un[pick].T, c.vloc, c.psi.T, c.eps, 0.69, c.shape,
+                                           c.h, 1e-10, 5000)
+    return dict(c=c, dc=dc, U=torch.tensor(Un, device=DEV), pick=pick, ref=ref)
+
+
+@pytest.mark.parametrize("width,pre", [(4, True), (4, False)])
+def test_block_cell24_matches_single_system_solver(cell24_block, width, pre):
+    # the benchmark's 24^3 cell and block of 64 trial vectors (1024 systems, 256 blocks of 4):
+    # block and single-system solves of the same systems give the same chi0 to the solver
+    # tolerance; every block is checked, through the output columns of every vector, and two
+    # columns of both against the oracle's plain DFPT (two solutions meeting tol 1e-10 differ
+    # by up to cond(A) tol, about 1e-8 at this frequency)
+    dc, U = cell24_block["dc"], cell24_block["U"]
     say("block chi0 24^3, 64 vectors, width", width, "precond", pre)
-    U = torch.tensor(np.random.default_rng(46).standard_normal((64, c.nd)), device=DEV)
     base = dict(cocg_tol=1e-10)
     a, rc_a, st_a = api.rpa_apply_chi0(dc, 0.69, U, base)
     b, rc_b, st_b = api.rpa_apply_chi0(dc, 0.69, U, dict(base, cocg_block=width,
@@ -205,6 +221,9 @@ def test_block_cell24_matches_single_system_solver(width, pre):
     say("iterations single %d block %d" % (st_a["cocg_iters_total"], st_b["cocg_iters_total"]))
     assert rc_a == 0 and rc_b == 0
     assert rel(b.cpu().numpy(), a.cpu().numpy()) < 1e-7
+    pick, ref = cell24_block["pick"], cell24_block["ref"]
+    for out in (a, b):
+        assert rel(out[pick].cpu().numpy().T, ref) < 1e-7
 
 
 def test_block_on_row_slabs_and_gemm_preconditioner():
