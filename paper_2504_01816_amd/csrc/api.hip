@@ -47,11 +47,12 @@ constexpr int kVersion = 10100;
 
 // RPA_MIXED: frequencies below this (Ha) solve in FP64.  Near the real axis the Sternheimer
 // shifts come close to the spectrum and the complex64 recurrences lose conjugacy: measured on
-// the 48^3 cell, complex64 needs 1.28x the FP64 iterations at omega = 0.311, 1.55x at 0.113
-// and 2.2x at 0.0203 (up to 5x for the orbitals next to the gap), against a per-iteration
-// saving of 1.45-1.6x; per block-apply the two tie at 0.311 and FP64 is 1.3x faster at 0.113
-// (on the 24^3 cell, where the kernel saves less per iteration, FP64 is already 1.16x faster
-// at 0.311).  The 8-point rule has no node between 0.113 and 0.311.
+// the 48^3 cell in subspace iterations after the first, complex64 needs 1.39x the FP64
+// iterations at omega = 0.311 and 1.78x at 0.113 (2x and more at 0.0203), against a
+// per-iteration saving of 1.45-1.6x: per block-apply complex64 is 1.04x faster at 0.311 and
+// FP64 1.21x faster at 0.113 (on the 24^3 cell, where the kernel saves less per iteration,
+// FP64 is already 1.16x faster at 0.311).  The 8-point rule has no node between 0.113 and
+// 0.311.
 constexpr double kMixedMinOmega = 0.2;
 
 // RPA_MIXED: default relative drop of the complex64 residual that triggers a reliable update.
@@ -254,8 +255,10 @@ struct Chi0Host {
 
 // Mixed precision: fewest COCG iterations between two reliable updates (besides the ones at the
 // tolerance and at the cap).  Fast-converging systems would otherwise refine every two or three
-// iterations (a refine_tol drop per step), each update a float64 sweep of 80 B per point; at
-// low frequency the updates are dozens of iterations apart and the gap does not bind.
+// iterations (a refine_tol drop per step), each update a float64 sweep of about 90 B per
+// point; at low frequency the updates are dozens of iterations apart and the gap does not
+// bind.  Measured on the 48^3 cell: a gap of 12 is 3-4% faster from omega = 1.4 up, a gap of 16
+// lets fast systems run 16 complex64 iterations past an update and breaks down at 49.4.
 constexpr int kRefineGap = 8;
 
 // COCG state kept in flight when the caller sets no cap: 128 GiB (under half the HBM of one
