@@ -18,9 +18,12 @@
 //    read and written by one thread only, so LDS is the sole cross-thread channel.
 //  * Large planes (whose whole-plane columns per thread would spill registers) are marched
 //    in row slabs, one after another, one column per thread: each slab's 6 rows above and
-//    below are read from memory for every centre plane (the vector they come from is not
-//    written in the same sweep), and each sweep ends with a workgroup-wide memory barrier,
-//    since the next sweep reads rows that other threads wrote.
+//    below are read from memory for every centre plane, and each sweep ends with a
+//    workgroup-wide memory barrier, since the next sweep reads rows that other threads wrote.
+//    In sweep 1 of the FP64 kernel the halo rows that belong to a slab marched earlier in the
+//    same sweep are read from the p_new that slab wrote (one vector instead of r and p; a
+//    memory barrier between slabs); the others are formed from r and p as the slab's own rows
+//    are.
 //  * Mixed precision (T = float): r, p and the partial solution x_lo are complex64; the
 //    solution x_hi and the residual r_hi are complex float64.  When the complex64 residual
 //    has dropped by refine_tol since the last update, at least refine_gap iterations after it
@@ -253,7 +256,7 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
     const bool hv = tid < nh;
     int hx = 0, lr = 0;
     unsigned hcol = 0;
-    bool hin = false;
+    bool hin = false, hdone = false;
     if (SLAB && hv) {
         const int hr = tid / a.n0;
         hx = tid - hr * a.n0;
@@ -267,12 +270,16 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
             hin = gy >= 0 && gy < a.n1;      // isolated box: rows beyond the walls are zero
         }
         hcol = unsigned(gy * a.n0 + hx);
+        // slabs run in order within a sweep: a row below the slab's first row belongs to a
+        // slab already marched in this sweep (lead.load_done may read what that slab wrote)
+        hdone = hin && gy < cl.y0;
     }
     typename Lead::Buf LB[Z][C];
     typename Cent::Buf CB[Z][C];
     typename Lead::Buf HB[Z];
     auto halo_load = [&](int zc) -> typename Lead::Buf {
-        return hin ? lead.load_at(zc, hcol) : typename Lead::Buf{};
+        if (!hin) return typename Lead::Buf{};
+        return hdone ? lead.load_done(zc, hcol) : lead.load_at(zc, hcol);
     };
     // warm-up: push planes -6 .. 5 through the top of the queue, Z at a time
 #pragma unroll 1
@@ -400,10 +407,10 @@ __device__ __forceinline__ void march(const Args& a, const Cols<C>& cl, Q2* lds,
 struct Empty {};
 
 // ---------------------------------------------------------------- sweep 1 (sigma)
-template <typename T2, int C, typename RA>
+template <typename T2, int C, typename RA, bool PN>
 struct LeadPnew {
     struct Buf { T2 r, p; };
-    const T2* r; const T2* pa; int P; const int* col; bool first; double dbr, dbi;
+    const T2* r; const T2* pa; const T2* pn; int P; const int* col; bool first; double dbr, dbi;
     __device__ Buf load(int z, int i, bool) const { return load_at(z, unsigned(col[i])); }
     __device__ Buf load_at(int z, unsigned gcol) const {
         const unsigned idx = unsigned(z * P) + gcol;
@@ -411,6 +418,19 @@ struct LeadPnew {
         b.r = ld(r, idx);
         b.p = first ? T2{0, 0} : ld(pa, idx);
         return b;
+    }
+    // a row of a slab marched earlier in this sweep: with PN its p_new is read from pn (the
+    // value make() would compute, rounded the same way), one load instead of two; make()
+    // returns it unchanged since p = 0
+    __device__ Buf load_done(int z, unsigned gcol) const {
+        if constexpr (PN) {
+            Buf b;
+            b.r = ld(pn, unsigned(z * P) + gcol);
+            b.p = T2{0, 0};
+            return b;
+        } else {
+            return load_at(z, gcol);
+        }
     }
     // p_new = r + beta p in the arithmetic precision, rounded once to the state precision
     __device__ T2 make(const Buf& b) const {
@@ -448,6 +468,7 @@ struct LeadLoad {
     const T2* v; int P; const int* col;
     __device__ Buf load(int z, int i, bool) const { return ld(v, unsigned(z * P + col[i])); }
     __device__ Buf load_at(int z, unsigned gcol) const { return ld(v, unsigned(z * P) + gcol); }
+    __device__ Buf load_done(int z, unsigned gcol) const { return load_at(z, gcol); }
     __device__ T2 make(const Buf& b) const { return b; }
 };
 // x stored as XS (double: real part only, double2: complex FP64, float2: complex64 x_lo);
@@ -498,6 +519,7 @@ struct LeadXlo {
     const float2* xlo; int P; const int* col;
     __device__ Buf load(int z, int i, bool) const { return ld(xlo, unsigned(z * P + col[i])); }
     __device__ Buf load_at(int z, unsigned gcol) const { return ld(xlo, unsigned(z * P) + gcol); }
+    __device__ Buf load_done(int z, unsigned gcol) const { return load_at(z, gcol); }
     __device__ float2 make(const Buf& b) const { return b; }
 };
 struct CentRhi {
@@ -557,6 +579,10 @@ void cocg_wg(Args a_in) {
     using T2 = typename Cplx<T>::type;
     using RA = typename Arith<T>::type;
     constexpr bool MIXED = std::is_same<T, float>::value;
+    // sweep 1 of the FP64 slab kernel reads the halo rows of slabs already marched from their
+    // p_new (measured at 48^3: 3.4% faster; the complex64 kernel, which saves half the bytes
+    // per row, ran 4.8% slower with the extra memory barrier per slab and keeps r and p)
+    constexpr bool PN = !MIXED;
     // Dispatch order: the host passes a permutation that starts the systems expected to need
     // the most iterations first (longest-first list scheduling: the easy ones then fill the
     // CUs behind them instead of leaving a long single-system tail).  Without one, orbitals
@@ -598,6 +624,18 @@ void cocg_wg(Args a_in) {
         if (SLAB) {
             make_cols<C>(a, sl, tid, BS, cl);
             if (sl > 0) lds_barrier();
+        }
+    };
+    // the same for sweep 1, whose halo rows of earlier slabs are read from the p_new those
+    // slabs wrote: their global stores are made visible to the whole workgroup as well
+    auto next_slab_pn = [&](int sl) {
+        if (SLAB) {
+            make_cols<C>(a, sl, tid, BS, cl);
+            if (sl > 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
         }
     };
 
@@ -651,10 +689,13 @@ void cocg_wg(Args a_in) {
                     }
             }
         }
-        LeadPnew<T2, C, RA> l1{r, pa, P, cl.col, first, beta_re, beta_im};
+        LeadPnew<T2, C, RA, PN> l1{r, pa, pb, P, cl.col, first, beta_re, beta_im};
         CentSigma<T2, C> c1{pb, P, cl.col, first, {0, 0, 0, 0, 0, 0, 0}};
         for (int sl = 0; sl < nslab; ++sl) {
-            next_slab(sl);
+            if constexpr (PN)
+                next_slab_pn(sl);
+            else
+                next_slab(sl);
             march<RA, T2, C, Z, SLAB>(a, cl, reinterpret_cast<T2*>(planes), eps_n, l1, c1, Q,
                                       carry);
         }

@@ -820,6 +820,7 @@ struct LeadSplit {   // the swept vector p, from its real and imaginary columns
         const unsigned idx = unsigned(z * P) + gcol;
         return double2{pr[idx], pi[idx]};
     }
+    __device__ Buf load_done(int z, unsigned gcol) const { return load_at(z, gcol); }
     __device__ double2 make(const Buf& b) const { return b; }
 };
 struct CentQ {       // stores q = A p, accumulates p^T q, |p|^2, |q|^2
