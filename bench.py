@@ -45,6 +45,34 @@ def host_driven_bytes(precond, block, shape):
     return b
 
 
+def subspace_converged(iters, ec_tol, cap):
+    """Per cell and frequency: whether the relative energy test held before the cap of `cap`
+    subspace iterations; None for a fixed count (ec_tol <= 0), which has no test."""
+    if ec_tol <= 0.0:
+        return None
+    return [[bool(k < cap) for k in row] for row in iters]
+
+
+def ec_label(iters, ec_tol, cap):
+    """What time_to_ec_s measures: a fixed subspace count, or the energy test, held at every
+    frequency or not."""
+    if ec_tol <= 0.0:
+        return "fixed count of %d subspace iterations per frequency" % cap
+    cv = subspace_converged(iters, ec_tol, cap)
+    n_cap = sum(1 for row in cv for c in row if not c)
+    if n_cap == 0:
+        return "energy test (ec_tol %g) held at every frequency" % ec_tol
+    return ("not converged: %d of %d frequencies stopped at the cap of %d subspace iterations "
+            "before the energy test (ec_tol %g) held" % (n_cap, sum(len(row) for row in cv),
+                                                         cap, ec_tol))
+
+
+def cycle_kernel_class(omega, precision, min_omega):
+    """The COCG kernel a cycle step at frequency omega runs: the precision's own, or FP64 for
+    a mixed step below mixed_min_omega."""
+    return precision if omega >= min_omega else "fp64"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,7 +296,7 @@ def run_cycle(args):
               else L.default_options().mixed_min_omega) if args.precision == "mixed" else 0.0
 
     def kclass(s):
-        return args.precision if wl.omegas[s["m"]] >= min_om else "fp64"
+        return cycle_kernel_class(wl.omegas[s["m"]], args.precision, min_om)
 
     def kernel_entry(p):
         tsteps = [s for s in steps if kclass(s) == p]
@@ -483,23 +511,10 @@ def run_energy(args):
     kernel = "cocg_wg (batched COCG, one workgroup per system)"
 
     def converged(iters):
-        # per cell and frequency: whether the relative energy test held before the cap (a
-        # fixed subspace count, ec_tol = 0, has no test and reports None)
-        if opts["ec_tol"] <= 0.0:
-            return None
-        cap = opts["subspace_iters"]
-        return [[bool(k < cap) for k in row] for row in iters]
+        return subspace_converged(iters, opts["ec_tol"], opts["subspace_iters"])
 
-    def ec_label(iters):
-        if opts["ec_tol"] <= 0.0:
-            return "fixed count of %d subspace iterations per frequency" % opts["subspace_iters"]
-        cv = converged(iters)
-        n_cap = sum(1 for row in cv for c in row if not c)
-        if n_cap == 0:
-            return "energy test (ec_tol %g) held at every frequency" % opts["ec_tol"]
-        return ("not converged: %d of %d frequencies stopped at the cap of %d subspace "
-                "iterations before the energy test (ec_tol %g) held" % (
-                    n_cap, sum(len(row) for row in cv), opts["subspace_iters"], opts["ec_tol"]))
+    def label(iters):
+        return ec_label(iters, opts["ec_tol"], opts["subspace_iters"])
     if args.precond or args.block >= 2:
         # the host-driven solvers: a launch is a whole solve of several kernels, and the
         # counters were taken on the plain kernel
@@ -522,7 +537,7 @@ def run_energy(args):
                    "freq_mode": args.freq_mode, "sq_order": args.sq_order,
                    "precond": bool(args.precond), "cocg_block": args.block},
         "time_to_ec_s": float(np.mean([s["fwd_s"] for s in steps])),
-        "time_to_ec_label": ec_label(steps[-1]["iters"]),
+        "time_to_ec_label": label(steps[-1]["iters"]),
         "backward_s": float(np.mean([s["bwd_s"] for s in steps])),
         "E_c": steps[-1]["E"],
         "subspace_iters": steps[-1]["iters"],
@@ -558,7 +573,7 @@ def run_energy(args):
             "chi0_block_applies_per_s": s2["applies"] / t,
             "time_to_ec_s": s2["fwd_s"], "backward_s": s2["bwd_s"],
             "E_c": s2["E"], "subspace_iters": s2["iters"], "converged": converged(s2["iters"]),
-            "time_to_ec_label": ec_label(s2["iters"]),
+            "time_to_ec_label": label(s2["iters"]),
             "E_c_rel_diff": [abs(a - b) / abs(b) for a, b in zip(s2["E"], steps[-1]["E"])],
             "cocg_alg_GBs": ALG_BYTES[other] * s2["point_iters"] / (s2["cocg_ms"] * 1e-3) / 1e9,
             "time_to_ec_ratio_vs_main": s2["fwd_s"] / out["time_to_ec_s"],
