@@ -213,20 +213,31 @@ def cmd_gaps(args):
 def cmd_krange(args):
     """Mean duration of one kernel's dispatches number a .. b-1 (in dispatch order) in a kernel
     trace: the dispatches of a bench run's timed region (bench.py prints their range), to set
-    beside the bench's own HIP-event timing of the same launches."""
+    beside the bench's own HIP-event timing of the same launches.  With --also, further
+    (kernel, first, last) ranges join the selection (a timed region that spans two kernels),
+    and a last row gives the mean over all of them."""
     fn = args.trace
     if os.path.isdir(fn):
         fn = sorted(glob.glob(os.path.join(fn, "**", "*kernel_trace.csv"), recursive=True))[0]
-    rows = sorted((r for r in csv.DictReader(open(fn)) if args.match in r["Kernel_Name"]),
-                  key=lambda r: int(r["Start_Timestamp"]))
-    sel = rows[args.first:args.last]
-    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in sel]
-    names = sorted(set(r["Kernel_Name"] for r in sel))
+    trace = list(csv.DictReader(open(fn)))
+    ranges = [(args.match, args.first, args.last)] + [(m, int(a), int(b)) for m, a, b in args.also]
     print("| kernel | dispatches in the trace | selected | mean ms | min ms | max ms |")
     print("|---|---|---|---|---|---|")
-    print("| `%s` | %d | %d .. %d | %.3f | %.3f | %.3f |" % (
-        short(names[0] if names else args.match, 90), len(rows), args.first, args.last - 1,
-        sum(d) / max(1, len(d)), min(d) if d else 0.0, max(d) if d else 0.0))
+    every = []
+    for match, first, last in ranges:
+        rows = sorted((r for r in trace if match in r["Kernel_Name"]),
+                      key=lambda r: int(r["Start_Timestamp"]))
+        sel = rows[first:last]
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in sel]
+        every += d
+        names = sorted(set(r["Kernel_Name"] for r in sel))
+        print("| `%s` | %d | %d .. %d | %.3f | %.3f | %.3f |" % (
+            short(names[0] if names else match, 90), len(rows), first, last - 1,
+            sum(d) / max(1, len(d)), min(d) if d else 0.0, max(d) if d else 0.0))
+    if len(ranges) > 1:
+        print("| all %d selected dispatches | | | %.3f | %.3f | %.3f |" % (
+            len(every), sum(every) / max(1, len(every)), min(every) if every else 0.0,
+            max(every) if every else 0.0))
 
 
 def read_counters(path):
@@ -362,6 +373,8 @@ def main():
     kr.add_argument("--match", required=True, help="substring of the kernel name")
     kr.add_argument("--first", type=int, required=True)
     kr.add_argument("--last", type=int, required=True)
+    kr.add_argument("--also", nargs=3, action="append", default=[],
+                    metavar=("MATCH", "FIRST", "LAST"), help="a further kernel range")
     gp = sub.add_parser("gaps")
     gp.add_argument("trace")
     gp.add_argument("--skip", type=int, default=0, help="leading dispatches to drop (set-up)")
