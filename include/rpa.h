@@ -154,9 +154,11 @@ typedef struct rpa_stats {
     double cocg_kernel_ms;        /* their summed duration, from HIP events recorded on the
                                      stream of each launch */
     double cocg_point_iters;      /* sum over systems of (COCG iterations x N_d) */
-    int32_t fp64_fallbacks;       /* RPA_MIXED: systems that reached cocg_max_iter in complex64
-                                     and were solved on in FP64 from where they stopped (up
-                                     to cocg_max_iter further iterations) */
+    int32_t fp64_fallbacks;       /* RPA_MIXED: systems that reached cocg_max_iter or broke
+                                     down in complex64 and were solved on in FP64 from where
+                                     they stopped, with the exact residual (up to
+                                     cocg_max_iter further iterations); only a second cap or
+                                     breakdown there counts in n_unconverged / n_breakdown */
     int32_t subspace_capped;      /* frequencies whose subspace iteration stopped at
                                      subspace_iters with ec_tol > 0 before
                                      |E_k - E_{k-1}| <= ec_tol |E_k| held (the energy
@@ -223,7 +225,8 @@ int rpa_apply_coulomb_noalloc(const rpa_cell* cell, int32_t power, int32_t nvec,
  *   in, out  device, N_d x nvec column-major float64 (must not overlap)
  *   stats    host, optional (NULL)
  * Returns RPA_ENOTCONV if any system hit cocg_max_iter (out still written),
- * RPA_EBREAKDOWN on a COCG breakdown.  Synchronises the stream (stats are host values).
+ * RPA_EBREAKDOWN on a COCG breakdown (RPA_MIXED: a complex64 breakdown is first restarted once
+ * in FP64 from the current iterate).  Synchronises the stream (stats are host values).
  */
 int rpa_apply_chi0(const rpa_cell* cell, double omega, int32_t nvec, const double* in,
                    double* out, const rpa_options* opt, rpa_stats* stats, void* ws,

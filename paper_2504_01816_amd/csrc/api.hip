@@ -774,20 +774,21 @@ int precond_setup(const rpa_cell* cell, const Grid& g, const Chi0Buf& b, Chi0Hos
     return RPA_OK;
 }
 
-// Mixed precision: the systems of a chunk that stopped at the iteration cap (complex64
-// recurrences can lose conjugacy on the most ill-conditioned shifts) are solved on in FP64 from
-// where they stopped: the mixed kernel leaves x_hi and the exact r_hi = b - A x_hi, and the
-// FP64 kernel solves A e = r_hi into x_hi += e to |r| <= tol |b|, with [r | p_a] and
-// [p_b | x_lo] of the mixed state as its two complex128 direction buffers.  Only the capped
-// systems are launched (the dispatch list is their indices).  Needs the host copy of the
-// statuses from tally().
+// Mixed precision: the systems of a chunk that stopped at the iteration cap or at a breakdown
+// of the complex64 recurrence (it can lose conjugacy on the most ill-conditioned shifts) are
+// solved on in FP64 from where they stopped, once (the restart of a broken-down COCG from its
+// current iterate and true residual): the mixed kernel leaves x_hi and the exact
+// r_hi = b - A x_hi, and the FP64 kernel solves A e = r_hi into x_hi += e to |r| <= tol |b|,
+// with [r | p_a] and [p_b | x_lo] of the mixed state as its two complex128 direction buffers.
+// Only those systems are launched (the dispatch list is their indices); a second breakdown or
+// the cap in FP64 is reported.  Needs the host copy of the statuses from tally().
 int continue_capped(const rpa_cell* cell, const Grid& g, const Opts& o, const Chi0Buf& b,
                     int nv, Chi0Host& h, SolveTally& t, hipStream_t s) {
     if (!b.mixed) return RPA_OK;
     const int S = cell->n_occ * nv;
     std::vector<int> capped;
     for (int i = 0; i < S; ++i)
-        if (h.st[i] == 1) capped.push_back(i);
+        if (h.st[i] == 1 || h.st[i] == 2) capped.push_back(i);
     if (capped.empty()) return RPA_OK;
     RPA_HIP(hipMemcpyAsync(b.order, capped.data(), sizeof(int) * capped.size(),
                            hipMemcpyHostToDevice, s));
@@ -830,7 +831,11 @@ int continue_capped(const rpa_cell* cell, const Grid& g, const Opts& o, const Ch
         t.point_iters += double(it[i]) * double(g.nd());
         t.iters_total += it[i];
         t.iters_max = std::max(t.iters_max, h.it[i] + it[i]);
-        t.unconv -= 1;                 // counted by tally() from the mixed stage
+        // counted by tally() from the mixed stage
+        if (h.st[i] == 1)
+            t.unconv -= 1;
+        else
+            t.breakdown -= 1;
         t.unconv += (st[i] == 1);
         t.breakdown += (st[i] == 2);
     }

@@ -11,6 +11,8 @@
 // precedence, and RPA_COCG_SHAPE="C,Z,bsmax[,bs[,occ[,nslab]]]" forces one (used by the
 // autotuner itself).  A forced shape that is not valid for the grid falls back to the
 // automatic choice.  RPA_COCG_VERBOSE=1 prints the chosen shape of every launch to stderr.
+// RPA_MIXED_BD_TOL replaces the complex64 kernel's breakdown threshold (1e-10; tests raise it to
+// force breakdowns and exercise the FP64 restart).
 #include <dlfcn.h>
 
 #include <cstdio>
@@ -217,6 +219,8 @@ hipError_t launch_cocg(const CocgLaunch& L, hipStream_t s) {
     a.vloc32 = L.vloc32;
     a.max_iter = L.max_iter;
     a.bd_tol = L.fp32 ? 1e-10 : 1e-14;
+    if (L.fp32)
+        if (const char* e = std::getenv("RPA_MIXED_BD_TOL")) a.bd_tol = std::atof(e);
     a.nd = L.g.nd();
     a.r = L.r;
     a.pa = L.pa;

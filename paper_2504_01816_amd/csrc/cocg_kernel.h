@@ -31,7 +31,9 @@
 //    replacement) runs: x_hi += x_lo and r_hi -= A x_lo, with
 //    A x_lo evaluated in float64 from the exact complex64 values, so r_hi = b - A x_hi holds
 //    to float64 rounding; then r <- complex64(r_hi).  p and the Krylov recurrence continue.
-//    The tolerance test uses |r_hi|.
+//    The tolerance test uses |r_hi|.  A solve that stops at the iteration cap or at a
+//    breakdown of the complex64 recurrence ends with a reliable update too, so the host can
+//    restart it in FP64 from x_hi and the exact residual.
 //  * Reductions accumulate in float64 and are fixed-order: results are bitwise
 //    reproducible run to run.
 // Layout: state arrays are system-major, nsys x N_d, complex interleaved (re, im).
@@ -547,7 +549,7 @@ struct CentRhi {
 };
 
 // x_hi <- x_hi + x_lo over the thread's own columns (a solve that stops without a final
-// reliable update: iteration cap or breakdown)
+// reliable update: a zero right-hand side, whose x_hi is written only here)
 template <int C>
 __device__ __forceinline__ void fold_xlo(const Args& a, const int (&col)[C], const bool (&valid)[C],
                                          double2* xhi, const float2* xlo, bool xhi_zero) {
@@ -753,44 +755,54 @@ void cocg_wg(Args a_in) {
             }
         }
         xlo_zero = false;
+        // mixed: reliable update (group-wise residual replacement): x_hi += x_lo and
+        // r_hi -= A x_lo in float64, then r = complex64(r_hi)
+        auto reliable_update = [&]() {
+            // drop the carried queue so that its registers are free for this sweep; the next
+            // sweep 1 reloads its first planes from memory
+#pragma unroll
+            for (int q = 0; q < 12 + Z; ++q)
+#pragma unroll
+                for (int i = 0; i < C; ++i) Q[q][i] = T2{0, 0};
+            cold = true;
+            float2 Qx[12 + 1][C];
+            LeadXlo lx{reinterpret_cast<const float2*>(a.xlo) + off, P, cl.col};
+            CentRhi cr{reinterpret_cast<double2*>(a.rhi) + off,
+                       reinterpret_cast<double2*>(a.x) + off, reinterpret_cast<float2*>(r),
+                       P, cl.col, xhi_zero, {0, 0, 0}};
+            for (int sl = 0; sl < nslab; ++sl) {
+                next_slab(sl);
+                march<double, float2, C, 1, SLAB>(a, cl, reinterpret_cast<float2*>(planes),
+                                                  eps_n, lx, cr, Qx, false);
+            }
+            slab_sync();
+            wg_reduce<3>(cr.acc, red);
+            xhi_zero = false;
+            xlo_zero = true;
+            ++nref;
+            acc2[0] = cr.acc[0]; acc2[1] = cr.acc[1]; acc2[2] = cr.acc[2];
+            rr_ref = acc2[2];
+            it_ref = it;
+        };
         if (zero_rhs) {
             done = true;
         } else if (breakdown) {
+            // mixed: a final reliable update leaves x_hi and the exact r_hi = b - A x_hi, from
+            // which the host restarts the system in FP64 (as after the iteration cap)
+            if constexpr (MIXED) reliable_update();
             st = 2;
             done = true;
         } else {
             bool conv = false;
+            bool updated = false;
             if constexpr (MIXED) {
                 // reliable update when the complex64 residual fell by refine_tol or hit tol,
                 // and at the iteration cap (so that a stopped solve leaves x_hi and the exact
                 // r_hi = b - A x_hi for an FP64 continuation)
                 if (acc2[2] <= tgt2 || it >= a.max_iter ||
                     (acc2[2] <= a.refine2 * rr_ref && it - it_ref >= a.refine_gap)) {
-                    // drop the carried queue so that its registers are free for this sweep;
-                    // the next sweep 1 reloads its first planes from memory
-#pragma unroll
-                    for (int q = 0; q < 12 + Z; ++q)
-#pragma unroll
-                        for (int i = 0; i < C; ++i) Q[q][i] = T2{0, 0};
-                    cold = true;
-                    float2 Qx[12 + 1][C];
-                    LeadXlo lx{reinterpret_cast<const float2*>(a.xlo) + off, P, cl.col};
-                    CentRhi cr{reinterpret_cast<double2*>(a.rhi) + off,
-                               reinterpret_cast<double2*>(a.x) + off, reinterpret_cast<float2*>(r),
-                               P, cl.col, xhi_zero, {0, 0, 0}};
-                    for (int sl = 0; sl < nslab; ++sl) {
-                        next_slab(sl);
-                        march<double, float2, C, 1, SLAB>(a, cl, reinterpret_cast<float2*>(planes),
-                                                          eps_n, lx, cr, Qx, false);
-                    }
-                    slab_sync();
-                    wg_reduce<3>(cr.acc, red);
-                    xhi_zero = false;
-                    xlo_zero = true;
-                    ++nref;
-                    acc2[0] = cr.acc[0]; acc2[1] = cr.acc[1]; acc2[2] = cr.acc[2];
-                    rr_ref = acc2[2];
-                    it_ref = it;
+                    reliable_update();
+                    updated = true;
                     conv = acc2[2] <= tgt2;
                 }
             } else {
@@ -804,6 +816,9 @@ void cocg_wg(Args a_in) {
             } else {
                 const double n2r = acc2[0] * acc2[0] + acc2[1] * acc2[1];
                 if (!(n2r > a.bd_tol * a.bd_tol * acc2[2] * acc2[2])) {
+                    if constexpr (MIXED) {
+                        if (!updated) reliable_update();
+                    }
                     st = 2;
                     done = true;
                 } else {

@@ -301,6 +301,35 @@ def test_mixed_capped_systems_continue_in_fp64(wl0, dc0):
     assert rel(gmx.cpu().numpy(), g64.cpu().numpy()) < 1e-7
 
 
+def test_mixed_breakdown_restarts_once_in_fp64(wl0, dc0, monkeypatch):
+    # A breakdown threshold that no bilinear form passes makes every complex64 solve break down
+    # at its first step: the kernel ends it with a reliable update (x_hi = 0, r_hi = b) and the
+    # library restarts it once in FP64 from there, the same recurrence as the FP64 path.  A
+    # threshold that trips part of the way restarts systems from a partial x_hi; compared with
+    # the oracle at cond(A) tol, since the restart begins a new Krylov space.
+    c = wl0.cells[0]
+    ns = c.psi.shape[0]
+    say("mixed chi0 with forced complex64 breakdowns: FP64 restart")
+    U = np.random.default_rng(23).standard_normal((4, c.nd))
+    Ut = torch.tensor(U, device=DEV)
+    o = dict(cocg_tol=1e-10, precision=MIXED, mixed_min_omega=0.0)
+    monkeypatch.setenv("RPA_MIXED_BD_TOL", "1e300")
+    mx, rc, st = api.rpa_apply_chi0(dc0, 0.5, Ut, o)
+    monkeypatch.delenv("RPA_MIXED_BD_TOL")
+    f64, rc2, st2 = api.rpa_apply_chi0(dc0, 0.5, Ut, dict(cocg_tol=1e-10))
+    say("first-step breakdowns: fallbacks", st["fp64_fallbacks"], "breakdowns", st["n_breakdown"])
+    assert rc == 0 and rc2 == 0 and st["n_breakdown"] == 0 and st["fp64_fallbacks"] == 4 * ns
+    assert rel(mx.cpu().numpy(), f64.cpu().numpy()) < 1e-12
+    ref, _, _ = ochi0.chi0_apply(U.T, c.vloc, c.psi.T, c.eps, 0.5, c.shape, c.h, 1e-10, 5000)
+    monkeypatch.setenv("RPA_MIXED_BD_TOL", "0.05")
+    mx2, rc3, st3 = api.rpa_apply_chi0(dc0, 0.5, Ut, o)
+    monkeypatch.delenv("RPA_MIXED_BD_TOL")
+    say("breakdowns part of the way: fallbacks", st3["fp64_fallbacks"], "refinements",
+        st3["refinements"])
+    assert rc3 == 0 and st3["n_breakdown"] == 0 and st3["fp64_fallbacks"] > 0
+    assert rel(mx2.cpu().numpy().T, ref) < 1e-7
+
+
 # ---------------------------------------------------------------------------- batched frequencies
 INDEPENDENT = 1
 
